@@ -1,0 +1,33 @@
+// vegas_common.hpp — host-side helpers shared by the handle API and the
+// serving scheduler (workspace layout, parameter preparation, combination).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "vegas_launch.hpp"
+#include "vegas_types.hpp"
+
+namespace vegas {
+
+// Byte offsets of one integral's device state inside its workspace.
+struct Layout {
+  size_t t, edges, hist, copies, rec64, rec32, partials, results, total;
+};
+
+const char* status_name(int s);
+bool shape_ok(int dim, int nb);
+Layout layout(int dim, int nb);
+DevGrid bind_grid(void* ws, int dim, int nb);
+// Derived integrand constants; VEGAS_OK or VEGAS_EINVAL. out may be NULL.
+int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArgs* out);
+// Workgroups for the iteration kernel: enough to fill the GPU at its
+// occupancy, no more than the events need, at most cap. -1 on HIP error.
+int default_blocks(const void* kernel, int threads, size_t lds, int64_t n_events, int cap);
+// Inverse-variance combination of iteration results and chi^2 per dof.
+void combine(const std::vector<double>& I_t, const std::vector<double>& s_t, double* I,
+             double* sigma, double* chi2);
+
+}  // namespace vegas

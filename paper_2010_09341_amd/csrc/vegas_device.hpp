@@ -1,0 +1,334 @@
+// vegas_device.hpp — device building blocks of one Vegas iteration on gfx950.
+//
+// The method (VegasFlow, arXiv:2010.09341, Sec. 1 and Sec. 3.1): points of the
+// unit hypercube are drawn through a per-dimension adaptive grid, the integrand
+// is evaluated on them, and the weights w = f(x) * J feed the estimate and the
+// grid's next refinement. Everything here runs per event in registers; the
+// grid records sit in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vegas_types.hpp"
+
+namespace vegas {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// -> 64-bit products of counter words 0 and 2 by fixed odd multipliers, the
+// high halves mixed into words 1 and 3 with the round key, the key advanced by
+// two Weyl increments between rounds. The key and the iteration word are
+// wave-uniform, so the compiler keeps them (and the first products that depend
+// only on them) on the scalar unit.
+// ---------------------------------------------------------------------------
+struct Words4 {
+  uint32_t v[4];
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t pa = (uint64_t)c0 * 0xD2511F53u;
+    const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
+    const uint32_t next0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+    const uint32_t next2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = next0;
+    c2 = next2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  Words4 out;
+  out.v[0] = c0;
+  out.v[1] = c1;
+  out.v[2] = c2;
+  out.v[3] = c3;
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Integrands in binary64. x[0..D) in the unit hypercube.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rambo24_f64(const double* x, const IntegrandArgs& P) {
+  const double sqrt_s = P.d[0], W = P.d[1], cut = P.d[2], two_pi = P.d[3];
+  if (P.mode == 1) return W;
+  double q[4][4];
+  double Q0 = 0.0, Qx = 0.0, Qy = 0.0, Qz = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double ct = 2.0 * x[4 * i] - 1.0;
+    const double st = sqrt(1.0 - ct * ct);
+    double sp, cp;
+    sincos(two_pi * x[4 * i + 1], &sp, &cp);
+    const double en = -log(x[4 * i + 2] * x[4 * i + 3]);
+    q[i][0] = en;
+    q[i][1] = en * st * cp;
+    q[i][2] = en * st * sp;
+    q[i][3] = en * ct;
+    Q0 += q[i][0];
+    Qx += q[i][1];
+    Qy += q[i][2];
+    Qz += q[i][3];
+  }
+  const double M = sqrt(Q0 * Q0 - Qx * Qx - Qy * Qy - Qz * Qz);
+  const double bx = -Qx / M, by = -Qy / M, bz = -Qz / M;
+  const double gam = Q0 / M;
+  const double a = 1.0 / (1.0 + gam);
+  const double xs = sqrt_s / M;
+  double p[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double bq = bx * q[i][1] + by * q[i][2] + bz * q[i][3];
+    p[i][0] = xs * (gam * q[i][0] + bq);
+    p[i][1] = xs * (q[i][1] + bx * q[i][0] + a * bq * bx);
+    p[i][2] = xs * (q[i][2] + by * q[i][0] + a * bq * by);
+    p[i][3] = xs * (q[i][3] + bz * q[i][0] + a * bq * bz);
+  }
+  double f = W;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int j = (i + 1) & 3;
+    const double sij =
+        2.0 * (p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3]);
+    if (!(sij > cut)) return 0.0;
+    f /= sij;
+  }
+  return f;
+}
+
+template <int FID>
+__device__ __forceinline__ double integrand_f64(const double* x, int D, const IntegrandArgs& P) {
+  if constexpr (FID == kConst) {
+    return 1.0;
+  } else if constexpr (FID == kSum) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < kMaxDim; ++d)
+      if (d < D) s += x[d];
+    return s;
+  } else if constexpr (FID == kGauss) {
+    // prod_d exp(-z_d^2/a^2)/(a sqrt(pi)) = exp(-sum z_d^2 / a^2 - D ln(a sqrt(pi)))
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < kMaxDim; ++d)
+      if (d < D) {
+        const double z = x[d] - P.c64[d];
+        acc += z * z;
+      }
+    return exp(P.d[1] - acc * P.d[0]);
+  } else if constexpr (FID == kLoToy) {
+    const double S = P.d[0], m2 = P.d[1], mG = P.d[2], norm = P.d[3], cut = P.d[4];
+    const double x1 = x[0], x2 = x[1];
+    const double c = 2.0 * x[2] - 1.0;
+    const double shat = x1 * x2 * S;
+    if (!(sqrt(shat) > cut)) return 0.0;
+    const double y1 = 1.0 - x1, y2 = 1.0 - x2;
+    const double g1 = y1 * y1 * y1 / sqrt(x1);
+    const double g2 = y2 * y2 * y2 / sqrt(x2);
+    const double dm = shat - m2;
+    const double bw = norm / (dm * dm + mG * mG);  // norm = (m G / pi) * 2 * 2 pi
+    return g1 * g2 * (1.0 + c * c) * bw / shat;
+  } else if constexpr (FID == kRambo24) {
+    return rambo24_f64(x, P);
+  } else {  // kBwFlat
+    const double z = x[0] - P.d[0];
+    return P.d[2] / (z * z + P.d[1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Integrands in binary32. Each returns f as a binary32 factor and, for the
+// Gaussian, its log2 (the factor is then 1), so that tails far below the
+// binary32 range still produce a binary64 weight.
+// ---------------------------------------------------------------------------
+struct F32Val {
+  float f;
+  float log2f;
+};
+
+__device__ __forceinline__ float rambo24_f32(const float* x, const IntegrandArgs& P) {
+  const float sqrt_s = P.f[0], W = P.f[1], cut = P.f[2];
+  if (P.mode == 1) return W;
+  float q[4][4];
+  float Q0 = 0.f, Qx = 0.f, Qy = 0.f, Qz = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float ct = fminf(fmaf(2.f, x[4 * i], -1.f), 1.f);
+    const float st = __builtin_sqrtf(fmaxf(fmaf(-ct, ct, 1.f), 0.f));
+    // v_sin_f32 / v_cos_f32 take their argument in turns: sin(2 pi u) = sin_turns(u)
+    const float sp = __builtin_amdgcn_sinf(x[4 * i + 1]);
+    const float cp = __builtin_amdgcn_cosf(x[4 * i + 1]);
+    // -ln(u u') = -log2(u u') * ln 2
+    const float en = fmaxf(-__builtin_amdgcn_logf(x[4 * i + 2] * x[4 * i + 3]) * 0.69314718f, 0.f);
+    q[i][0] = en;
+    q[i][1] = en * st * cp;
+    q[i][2] = en * st * sp;
+    q[i][3] = en * ct;
+    Q0 += q[i][0];
+    Qx += q[i][1];
+    Qy += q[i][2];
+    Qz += q[i][3];
+  }
+  const float M2 = Q0 * Q0 - Qx * Qx - Qy * Qy - Qz * Qz;
+  const float iM = __builtin_amdgcn_rsqf(M2);
+  const float bx = -Qx * iM, by = -Qy * iM, bz = -Qz * iM;
+  const float gam = Q0 * iM;
+  const float a = __builtin_amdgcn_rcpf(1.f + gam);
+  const float xs = sqrt_s * iM;
+  float p[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float bq = bx * q[i][1] + by * q[i][2] + bz * q[i][3];
+    const float abq = a * bq;
+    p[i][0] = xs * (gam * q[i][0] + bq);
+    p[i][1] = xs * (q[i][1] + bx * (q[i][0] + abq));
+    p[i][2] = xs * (q[i][2] + by * (q[i][0] + abq));
+    p[i][3] = xs * (q[i][3] + bz * (q[i][0] + abq));
+  }
+  float prod = 1.f;
+  bool pass = true;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int j = (i + 1) & 3;
+    const float sij =
+        2.f * (p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3]);
+    pass = pass && (sij > cut);
+    prod *= sij;
+  }
+  return pass ? W * __builtin_amdgcn_rcpf(prod) : 0.f;
+}
+
+template <int FID>
+__device__ __forceinline__ F32Val integrand_f32(const float* x, int D, const IntegrandArgs& P) {
+  F32Val r{1.f, 0.f};
+  if constexpr (FID == kConst) {
+  } else if constexpr (FID == kSum) {
+    float s = 0.f;
+#pragma unroll
+    for (int d = 0; d < kMaxDim; ++d)
+      if (d < D) s += x[d];
+    r.f = s;
+  } else if constexpr (FID == kGauss) {
+    // log2 f = -(log2 e / a^2) sum z^2 - D log2(a sqrt(pi))
+    float acc = 0.f;
+#pragma unroll
+    for (int d = 0; d < kMaxDim; ++d)
+      if (d < D) {
+        const float z = x[d] - P.c32[d];
+        acc = fmaf(z, z, acc);
+      }
+    r.log2f = fmaf(-P.f[0], acc, P.f[1]);
+  } else if constexpr (FID == kLoToy) {
+    const float S = P.f[0], m2 = P.f[1], mG = P.f[2], norm = P.f[3], cut2 = P.f[4];
+    const float x1 = x[0], x2 = x[1];
+    const float c = fmaf(2.f, x[2], -1.f);
+    const float shat = x1 * x2 * S;
+    const float y1 = 1.f - x1, y2 = 1.f - x2;
+    const float g12 = (y1 * y1 * y1) * (y2 * y2 * y2) * __builtin_amdgcn_rsqf(x1 * x2);
+    const float dm = shat - m2;
+    const float den = fmaf(dm, dm, mG * mG) * shat;
+    const float v = g12 * fmaf(c, c, 1.f) * norm * __builtin_amdgcn_rcpf(den);
+    r.f = (shat > cut2) ? v : 0.f;
+  } else if constexpr (FID == kRambo24) {
+    r.f = rambo24_f32(x, P);
+  } else {  // kBwFlat
+    const float z = x[0] - P.f[0];
+    r.f = P.f[2] * __builtin_amdgcn_rcpf(fmaf(z, z, P.f[1]));
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// One event: draw, map, evaluate. Returns w = f(x) * J in binary64 and the
+// bin index of every dimension in bins[] (offset by d * nb, i.e. the LDS
+// histogram cell).
+// ---------------------------------------------------------------------------
+template <int NBLK, int FID, int PREC>
+__device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
+                                               int D, uint32_t nb, const void* srec,
+                                               const IntegrandArgs& P, int* bins) {
+  constexpr int DMAX = 4 * NBLK;
+  const uint32_t n_lo = (uint32_t)n, n_hi = (uint32_t)(n >> 32);
+  if constexpr (PREC == kFp64) {
+    const Rec64* rec = static_cast<const Rec64*>(srec);
+    double x[DMAX];
+    double jac = 1.0;
+    const double nbf = (double)nb;
+#pragma unroll
+    for (int j = 0; j < NBLK; ++j) {
+      if (4 * j < D) {
+        const Words4 r = philox4x32_10(n_lo, n_hi, t, (uint32_t)j, k0, k1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int d = 4 * j + i;
+          if (d < D) {
+            const uint64_t prod = (uint64_t)r.v[i] * nb;
+            const int k = (int)(prod >> 32);
+            const uint32_t rem = (uint32_t)prod;
+            // (rem + 1/2) 2^-32, exact in binary64
+            const double frac = fma((double)rem, 0x1p-32, 0x1p-33);
+            const int cell = d * (int)nb + k;
+            const Rec64 g = rec[cell];
+            x[d] = fma(frac, g.w, g.e);
+            jac *= nbf * g.w;
+            bins[d] = cell;
+          }
+        }
+      }
+    }
+    return integrand_f64<FID>(x, D, P) * jac;
+  } else {
+    const Rec32* rec = static_cast<const Rec32*>(srec);
+    float x[DMAX];
+    float l2j = 0.f;
+#pragma unroll
+    for (int j = 0; j < NBLK; ++j) {
+      if (4 * j < D) {
+        const Words4 r = philox4x32_10(n_lo, n_hi, t, (uint32_t)j, k0, k1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int d = 4 * j + i;
+          if (d < D) {
+            const uint64_t prod = (uint64_t)r.v[i] * nb;
+            const int k = (int)(prod >> 32);
+            const uint32_t rem = (uint32_t)prod;
+            // centre of the 2^-23 cell: ((rem >> 9) + 1/2) 2^-23, exact in binary32
+            const float frac = (float)((rem >> 8) | 1u) * 0x1p-24f;
+            const int cell = d * (int)nb + k;
+            const Rec32 g = rec[cell];
+            x[d] = fmaf(frac, g.w, g.e);
+            l2j += g.l2j;
+            bins[d] = cell;
+          }
+        }
+      }
+    }
+    const F32Val v = integrand_f32<FID>(x, D, P);
+    // w = f * 2^(log2 J + log2 f), the power split into a binary32 mantissa
+    // in [1, 2) and an integer exponent applied in binary64.
+    const float l2 = l2j + v.log2f;
+    const float fl = __builtin_floorf(l2);
+    const double m = (double)__builtin_amdgcn_exp2f(l2 - fl);
+    return (double)v.f * __builtin_ldexp(m, (int)fl);
+  }
+}
+
+}  // namespace vegas

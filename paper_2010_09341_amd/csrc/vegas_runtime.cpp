@@ -1,0 +1,700 @@
+// vegas_runtime.cpp — handles and the C interface of libvegas.so (declared in
+// include/vegas.h). Host code only: argument validation, device memory,
+// launch configuration and the inverse-variance combination of iterations;
+// every per-event and per-bin step runs in the kernels of vegas_kernels.hip.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "vegas.h"
+#include "vegas_common.hpp"
+#include "vegas_types.hpp"
+#include "vegas_launch.hpp"
+
+using vegas::DevGrid;
+using vegas::IntegrandArgs;
+
+namespace vegas {
+
+const char* status_name(int s) {
+  switch (s) {
+    case VEGAS_OK: return "ok";
+    case VEGAS_EINVAL: return "invalid argument";
+    case VEGAS_ENOMEM: return "out of memory";
+    case VEGAS_EDEVICE: return "device error";
+    case VEGAS_ESTATE: return "invalid state";
+    case VEGAS_ENONFINITE: return "non-finite weights";
+    case VEGAS_EBUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+bool shape_ok(int dim, int nb) {
+  return dim >= 1 && dim <= VEGAS_MAX_DIM && nb >= 2 && nb <= VEGAS_MAX_BINS &&
+         dim * nb <= VEGAS_MAX_CELLS;
+}
+
+Layout layout(int dim, int nb) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  Layout L;
+  size_t o = 0;
+  L.t = o;
+  o += 256;
+  L.edges = o;
+  o = al(o + sizeof(double) * dim * (nb + 1));
+  L.hist = o;
+  o = al(o + sizeof(double) * dim * nb);
+  L.copies = o;
+  o = al(o + sizeof(double) * kHistCopies * dim * nb);
+  L.rec64 = o;
+  o = al(o + sizeof(Rec64) * dim * nb);
+  L.rec32 = o;
+  o = al(o + sizeof(Rec32) * dim * nb);
+  L.partials = o;
+  o = al(o + sizeof(double) * 4 * kMaxBlocks);
+  L.results = o;
+  o = al(o + sizeof(double) * 4 * kRing);
+  L.total = o;
+  return L;
+}
+
+DevGrid bind_grid(void* ws, int dim, int nb) {
+  const Layout L = layout(dim, nb);
+  char* b = static_cast<char*>(ws);
+  DevGrid g;
+  g.dim = dim;
+  g.nb = nb;
+  g.t = reinterpret_cast<uint32_t*>(b + L.t);
+  g.edges = reinterpret_cast<double*>(b + L.edges);
+  g.hist = reinterpret_cast<double*>(b + L.hist);
+  g.copies = reinterpret_cast<double*>(b + L.copies);
+  g.rec64 = b + L.rec64;
+  g.rec32 = b + L.rec32;
+  g.partials = reinterpret_cast<double*>(b + L.partials);
+  g.results = reinterpret_cast<double*>(b + L.results);
+  g.max_blocks = kMaxBlocks;
+  g.ring = kRing;
+  return g;
+}
+
+// Derived integrand constants from the user's parameters (the parameter
+// conventions are those listed with the VEGAS_F_* identifiers).
+int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArgs* out) {
+  IntegrandArgs a;
+  std::memset(&a, 0, sizeof(a));
+  auto par = [&](int i, double dflt) { return (p && i < np) ? p[i] : dflt; };
+  const double pi = 3.14159265358979323846;
+  if (np < 0 || np > VEGAS_MAX_PARAMS || (np > 0 && !p)) return VEGAS_EINVAL;
+  for (int i = 0; i < np; ++i)
+    if (!std::isfinite(p[i])) return VEGAS_EINVAL;
+  switch (fid) {
+    case VEGAS_F_CONST:
+    case VEGAS_F_SUM:
+      if (np != 0) return VEGAS_EINVAL;
+      break;
+    case VEGAS_F_GAUSS: {
+      if (!(np == 0 || np == 1 || np == 1 + dim)) return VEGAS_EINVAL;
+      const double w = par(0, 0.1);
+      if (!(w > 0.0)) return VEGAS_EINVAL;
+      a.d[0] = 1.0 / (w * w);
+      a.d[1] = -dim * std::log(w * std::sqrt(pi));
+      a.f[0] = (float)(1.0 / (std::log(2.0) * w * w));
+      a.f[1] = (float)(-dim * std::log2(w * std::sqrt(pi)));
+      for (int d = 0; d < dim; ++d) {
+        const double c = (np == 1 + dim) ? p[1 + d] : 0.5;
+        a.c64[d] = c;
+        a.c32[d] = (float)c;
+      }
+      break;
+    }
+    case VEGAS_F_LO_TOY: {
+      if (dim != 4 || np > 4) return VEGAS_EINVAL;
+      const double sqrt_s = par(0, 13000.0), m = par(1, 91.19), G = par(2, 2.5),
+                   cut = par(3, 20.0);
+      if (!(sqrt_s > 0.0) || !(m > 0.0) || !(G > 0.0)) return VEGAS_EINVAL;
+      a.d[0] = sqrt_s * sqrt_s;
+      a.d[1] = m * m;
+      a.d[2] = m * G;
+      a.d[3] = (m * G / pi) * 2.0 * (2.0 * pi);
+      a.d[4] = cut;
+      for (int i = 0; i < 4; ++i) a.f[i] = (float)a.d[i];
+      a.f[4] = cut > 0.0 ? (float)(cut * cut) : -1.0f;
+      break;
+    }
+    case VEGAS_F_RAMBO24: {
+      if (dim != 16 || np > 3) return VEGAS_EINVAL;
+      const double sqrt_s = par(0, 1000.0), cut_frac = par(1, 0.01), mode = par(2, 0.0);
+      if (!(sqrt_s > 0.0) || !(mode == 0.0 || mode == 1.0)) return VEGAS_EINVAL;
+      const double s = sqrt_s * sqrt_s;
+      a.d[0] = sqrt_s;
+      a.d[1] = (pi / 2.0) * (pi / 2.0) * (pi / 2.0) * s * s / 12.0;
+      a.d[2] = cut_frac * s;
+      a.d[3] = 2.0 * pi;
+      a.f[0] = (float)a.d[0];
+      a.f[1] = (float)a.d[1];
+      a.f[2] = (float)a.d[2];
+      a.mode = (int)mode;
+      break;
+    }
+    case VEGAS_F_BW_FLAT: {
+      if (np > 2) return VEGAS_EINVAL;
+      const double m = par(0, 0.5), G = par(1, 0.02);
+      if (!(G > 0.0)) return VEGAS_EINVAL;
+      a.d[0] = m;
+      a.d[1] = G * G / 4.0;
+      a.d[2] = G / (2.0 * pi);
+      for (int i = 0; i < 3; ++i) a.f[i] = (float)a.d[i];
+      break;
+    }
+    default:
+      return VEGAS_EINVAL;
+  }
+  if (out) *out = a;
+  return VEGAS_OK;
+}
+
+int default_blocks(const void* kernel, int threads, size_t lds, int64_t n_events, int cap) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  static int cus = 0;
+  int per_cu = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (cus == 0) {
+      int dev = 0;
+      hipDeviceProp_t prop;
+      if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return -1;
+      cus = prop.multiProcessorCount;
+    }
+    auto key = std::make_pair(kernel, threads * 65536 + (int)(lds / 256));
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+      int n = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, lds) != hipSuccess)
+        return -1;
+      cache[key] = n;
+      per_cu = n;
+    } else {
+      per_cu = it->second;
+    }
+  }
+  int64_t want = (n_events + threads - 1) / threads;
+  int64_t fill = (int64_t)std::max(per_cu, 1) * cus;
+  int64_t b = std::min<int64_t>(want, fill);
+  b = std::min<int64_t>(b, cap);
+  return (int)std::max<int64_t>(b, 1);
+}
+
+void combine(const std::vector<double>& I_t, const std::vector<double>& s_t, double* I,
+             double* sigma, double* chi2) {
+  const size_t n = I_t.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!(s_t[i] > 0.0)) {
+      *I = I_t[i];
+      *sigma = 0.0;
+      *chi2 = 0.0;
+      return;
+    }
+  double sw = 0.0, swi = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    const double w = 1.0 / (s_t[i] * s_t[i]);
+    sw += w;
+    swi += w * I_t[i];
+  }
+  const double mean = swi / sw;
+  double c2 = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    const double z = (I_t[i] - mean) / s_t[i];
+    c2 += z * z;
+  }
+  *I = mean;
+  *sigma = 1.0 / std::sqrt(sw);
+  *chi2 = n > 1 ? c2 / (double)(n - 1) : 0.0;
+}
+
+}  // namespace vegas
+
+using namespace vegas;
+
+struct vegas_ctx {
+  int device = 0;
+  int dim = 0, nb = 0, prec = VEGAS_FP64;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  void* own_ws = nullptr;
+  void* ws = nullptr;
+  DevGrid g;
+  double* pinned = nullptr;
+  size_t pinned_n = 0;
+  uint32_t t = 0;
+  bool hist_valid = false;
+  bool poisoned = false;
+  std::vector<double> I_t, s_t;
+  int64_t last_bad = 0;
+  std::vector<double> params[VEGAS_N_INTEGRANDS];
+  int max_blocks = 0;
+  int threads = 256;
+  bool timing = false;
+  double time_ms = 0.0;
+  int64_t n_timed = 0;
+  std::vector<hipEvent_t> events;
+  double* dump_buf = nullptr;
+  size_t dump_n = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess || prev == dev || hipSetDevice(dev) != hipSuccess)
+      prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int fail(vegas_h h, hipError_t e) {
+  if (e == hipSuccess) return VEGAS_OK;
+  if (h) h->poisoned = true;
+  return VEGAS_EDEVICE;
+}
+
+#define VEGAS_TRY(h, expr)                 \
+  do {                                     \
+    hipError_t _e = (expr);                \
+    if (_e != hipSuccess) return fail(h, _e); \
+  } while (0)
+
+int ready(vegas_h h) {
+  if (!h) return VEGAS_EINVAL;
+  if (h->poisoned) return VEGAS_EDEVICE;
+  return VEGAS_OK;
+}
+
+int integrand_args(vegas_h h, int fid, IntegrandArgs* a) {
+  if (fid < 0 || fid >= VEGAS_N_INTEGRANDS) return VEGAS_EINVAL;
+  const std::vector<double>& p = h->params[fid];
+  int rc = build_integrand_args(fid, h->dim, p.empty() ? nullptr : p.data(), (int)p.size(), a);
+  if (rc != VEGAS_OK) return rc;
+  if (!iterate_kernel(fid, h->prec, h->dim, false)) return VEGAS_EINVAL;
+  return VEGAS_OK;
+}
+
+hipError_t ensure_events(vegas_h h, size_t n) {
+  while (h->events.size() < n) {
+    hipEvent_t e;
+    hipError_t rc = hipEventCreate(&e);
+    if (rc != hipSuccess) return rc;
+    h->events.push_back(e);
+  }
+  return hipSuccess;
+}
+
+int blocks_for(vegas_h h, int fid, int64_t n_events) {
+  const void* k = iterate_kernel(fid, h->prec, h->dim, false);
+  const int cap = h->max_blocks > 0 ? std::min(h->max_blocks, kMaxBlocks) : kMaxBlocks;
+  return default_blocks(k, h->threads, iterate_lds_bytes(h->dim, h->nb), n_events, cap);
+}
+
+// Enqueue iterate + finalize (+ refine) for one iteration; event slots 2i, 2i+1
+// bracket the iteration kernel when timing is on.
+hipError_t enqueue_iteration(vegas_h h, int fid, const IntegrandArgs& P, int64_t n_events,
+                             uint64_t seed, int blocks, size_t ev_slot, bool refine,
+                             double alpha) {
+  IterLaunch L;
+  L.fid = fid;
+  L.prec = h->prec;
+  L.n_events = n_events;
+  L.seed = seed;
+  L.blocks = blocks;
+  L.threads = h->threads;
+  hipError_t e;
+  if (h->timing && (e = hipEventRecord(h->events[2 * ev_slot], h->stream)) != hipSuccess) return e;
+  if ((e = launch_iterate(h->g, L, P, h->stream)) != hipSuccess) return e;
+  if (h->timing && (e = hipEventRecord(h->events[2 * ev_slot + 1], h->stream)) != hipSuccess)
+    return e;
+  if ((e = launch_finalize(h->g, blocks, n_events, h->stream)) != hipSuccess) return e;
+  if (refine && (e = launch_refine(h->g, alpha, h->stream)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t collect_timing(vegas_h h, size_t n) {
+  if (!h->timing) return hipSuccess;
+  for (size_t i = 0; i < n; ++i) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, h->events[2 * i], h->events[2 * i + 1]);
+    if (e != hipSuccess) return e;
+    h->time_ms += ms;
+    h->n_timed += 1;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vegas_strerror(int status) { return status_name(status); }
+
+int vegas_workspace_bytes(int dim, int n_bins, size_t* bytes) {
+  if (!shape_ok(dim, n_bins) || !bytes) return VEGAS_EINVAL;
+  *bytes = layout(dim, n_bins).total;
+  return VEGAS_OK;
+}
+
+int vegas_create(int dim, int n_bins, vegas_h* out) {
+  if (!out || !shape_ok(dim, n_bins)) return VEGAS_EINVAL;
+  *out = nullptr;
+  vegas_h h = new (std::nothrow) vegas_ctx();
+  if (!h) return VEGAS_ENOMEM;
+  h->dim = dim;
+  h->nb = n_bins;
+  int rc = VEGAS_OK;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    h->stream = h->own_stream;
+    e = hipMalloc(&h->own_ws, layout(dim, n_bins).total);
+    if (e == hipErrorOutOfMemory) rc = VEGAS_ENOMEM;
+  }
+  if (e == hipSuccess) {
+    h->ws = h->own_ws;
+    h->g = bind_grid(h->ws, dim, n_bins);
+    h->pinned_n = std::max<size_t>(4 * kRing, (size_t)dim * (n_bins + 1));
+    e = hipHostMalloc(reinterpret_cast<void**>(&h->pinned), sizeof(double) * h->pinned_n,
+                      hipHostMallocDefault);
+  }
+  if (e == hipSuccess) e = launch_init_grid(h->g, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    vegas_destroy(h);
+    return rc != VEGAS_OK ? rc : VEGAS_EDEVICE;
+  }
+  *out = h;
+  return VEGAS_OK;
+}
+
+int vegas_destroy(vegas_h h) {
+  if (!h) return VEGAS_OK;
+  DeviceGuard dg(h->device);
+  // teardown: errors are ignored, the handle goes away regardless
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  if (h->dump_buf) (void)hipFree(h->dump_buf);
+  if (h->own_ws) (void)hipFree(h->own_ws);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+  delete h;
+  return VEGAS_OK;
+}
+
+int vegas_reset(vegas_h h) {
+  int rc = ready(h);
+  if (rc) return rc;
+  DeviceGuard dg(h->device);
+  VEGAS_TRY(h, launch_init_grid(h->g, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  h->t = 0;
+  h->hist_valid = false;
+  h->I_t.clear();
+  h->s_t.clear();
+  h->last_bad = 0;
+  return VEGAS_OK;
+}
+
+int vegas_set_params(vegas_h h, int integrand_id, const double* params, int n_params) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (integrand_id < 0 || integrand_id >= VEGAS_N_INTEGRANDS) return VEGAS_EINVAL;
+  rc = build_integrand_args(integrand_id, h->dim, params, n_params, nullptr);
+  if (rc) return rc;
+  h->params[integrand_id].assign(params, params + n_params);
+  return VEGAS_OK;
+}
+
+int vegas_set_precision(vegas_h h, int prec) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (prec != VEGAS_FP64 && prec != VEGAS_FP32_EVAL) return VEGAS_EINVAL;
+  h->prec = prec;
+  return VEGAS_OK;
+}
+
+int vegas_bind_stream(vegas_h h, void* hip_stream) {
+  int rc = ready(h);
+  if (rc) return rc;
+  DeviceGuard dg(h->device);
+  hipStream_t next = hip_stream ? static_cast<hipStream_t>(hip_stream) : h->own_stream;
+  if (next != h->stream) {
+    // order the new stream after everything queued on the old one
+    VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+    h->stream = next;
+  }
+  return VEGAS_OK;
+}
+
+int vegas_bind_workspace(vegas_h h, void* dev_ptr, size_t bytes) {
+  int rc = ready(h);
+  if (rc) return rc;
+  const size_t need = layout(h->dim, h->nb).total;
+  void* next = dev_ptr ? dev_ptr : h->own_ws;
+  if (dev_ptr && (bytes < need || (reinterpret_cast<uintptr_t>(dev_ptr) & 255)))
+    return VEGAS_EINVAL;
+  DeviceGuard dg(h->device);
+  if (!next) {
+    VEGAS_TRY(h, hipMalloc(&h->own_ws, need));
+    next = h->own_ws;
+  }
+  if (next != h->ws) {
+    VEGAS_TRY(h, hipMemcpyAsync(next, h->ws, need, hipMemcpyDeviceToDevice, h->stream));
+    VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+    h->ws = next;
+    h->g = bind_grid(h->ws, h->dim, h->nb);
+    // records hold no pointers, the copy preserved everything
+  }
+  if (dev_ptr && h->own_ws) {
+    VEGAS_TRY(h, hipFree(h->own_ws));
+    h->own_ws = nullptr;
+  }
+  return VEGAS_OK;
+}
+
+int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, double* I,
+                  double* sigma) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (n_events < 2 || !I || !sigma) return VEGAS_EINVAL;
+  IntegrandArgs P;
+  rc = integrand_args(h, integrand_id, &P);
+  if (rc) return rc;
+  DeviceGuard dg(h->device);
+  const int blocks = blocks_for(h, integrand_id, n_events);
+  if (blocks < 1) return fail(h, hipErrorInvalidValue);
+  if (h->timing) VEGAS_TRY(h, ensure_events(h, 2));
+  VEGAS_TRY(h, enqueue_iteration(h, integrand_id, P, n_events, seed, blocks, 0, false, 0.0));
+  const size_t slot = h->t % kRing;
+  VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.results + 4 * slot, 4 * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  VEGAS_TRY(h, collect_timing(h, 1));
+  *I = h->pinned[0];
+  *sigma = h->pinned[1];
+  h->last_bad = (int64_t)h->pinned[2];
+  h->t += 1;
+  h->hist_valid = true;
+  h->I_t.push_back(*I);
+  h->s_t.push_back(*sigma);
+  return h->last_bad > 0 ? VEGAS_ENONFINITE : VEGAS_OK;
+}
+
+int vegas_refine(vegas_h h, double alpha) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!(alpha >= 0.0 && alpha <= VEGAS_MAX_ALPHA)) return VEGAS_EINVAL;
+  if (!h->hist_valid) return VEGAS_ESTATE;
+  DeviceGuard dg(h->device);
+  VEGAS_TRY(h, launch_refine(h->g, alpha, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  h->hist_valid = false;
+  return VEGAS_OK;
+}
+
+int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int n_iter,
+              double alpha, double* I_t, double* sigma_t) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (n_events < 2 || n_iter < 1 || n_iter > VEGAS_MAX_RUN_ITER ||
+      !(alpha >= 0.0 && alpha <= VEGAS_MAX_ALPHA))
+    return VEGAS_EINVAL;
+  IntegrandArgs P;
+  rc = integrand_args(h, integrand_id, &P);
+  if (rc) return rc;
+  DeviceGuard dg(h->device);
+  const int blocks = blocks_for(h, integrand_id, n_events);
+  if (blocks < 1) return fail(h, hipErrorInvalidValue);
+  if (h->timing) VEGAS_TRY(h, ensure_events(h, 2 * (size_t)n_iter));
+  for (int i = 0; i < n_iter; ++i)
+    VEGAS_TRY(h, enqueue_iteration(h, integrand_id, P, n_events, seed, blocks, i, i + 1 < n_iter,
+                                   alpha));
+  VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.results, 4 * sizeof(double) * kRing,
+                              hipMemcpyDeviceToHost, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  VEGAS_TRY(h, collect_timing(h, (size_t)n_iter));
+  int64_t bad = 0;
+  for (int i = 0; i < n_iter; ++i) {
+    const double* r = h->pinned + 4 * ((h->t + i) % kRing);
+    if (I_t) I_t[i] = r[0];
+    if (sigma_t) sigma_t[i] = r[1];
+    h->I_t.push_back(r[0]);
+    h->s_t.push_back(r[1]);
+    bad += (int64_t)r[2];
+  }
+  h->t += (uint32_t)n_iter;
+  h->hist_valid = true;
+  h->last_bad = bad;
+  return bad > 0 ? VEGAS_ENONFINITE : VEGAS_OK;
+}
+
+int vegas_result(vegas_h h, double* I, double* sigma, double* chi2_dof) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!I || !sigma || !chi2_dof) return VEGAS_EINVAL;
+  if (h->I_t.empty()) return VEGAS_ESTATE;
+  combine(h->I_t, h->s_t, I, sigma, chi2_dof);
+  return VEGAS_OK;
+}
+
+int vegas_get_grid(vegas_h h, double* edges, size_t n) {
+  int rc = ready(h);
+  if (rc) return rc;
+  const size_t need = (size_t)h->dim * (h->nb + 1);
+  if (!edges || n != need) return VEGAS_EINVAL;
+  DeviceGuard dg(h->device);
+  VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.edges, need * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  std::memcpy(edges, h->pinned, need * sizeof(double));
+  return VEGAS_OK;
+}
+
+int vegas_set_grid(vegas_h h, const double* edges, size_t n) {
+  int rc = ready(h);
+  if (rc) return rc;
+  const size_t need = (size_t)h->dim * (h->nb + 1);
+  if (!edges || n != need) return VEGAS_EINVAL;
+  for (int d = 0; d < h->dim; ++d) {
+    const double* e = edges + (size_t)d * (h->nb + 1);
+    if (e[0] != 0.0 || e[h->nb] != 1.0) return VEGAS_EINVAL;
+    for (int i = 0; i < h->nb; ++i)
+      if (!(e[i + 1] > e[i])) return VEGAS_EINVAL;
+  }
+  DeviceGuard dg(h->device);
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  std::memcpy(h->pinned, edges, need * sizeof(double));
+  VEGAS_TRY(h, hipMemcpyAsync(h->g.edges, h->pinned, need * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
+  VEGAS_TRY(h, launch_prepare(h->g, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  return VEGAS_OK;
+}
+
+int vegas_get_hist(vegas_h h, double* hist, size_t n) {
+  int rc = ready(h);
+  if (rc) return rc;
+  const size_t need = (size_t)h->dim * h->nb;
+  if (!hist || n != need) return VEGAS_EINVAL;
+  DeviceGuard dg(h->device);
+  VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.hist, need * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  std::memcpy(hist, h->pinned, need * sizeof(double));
+  return VEGAS_OK;
+}
+
+int vegas_set_hist(vegas_h h, const double* hist, size_t n) {
+  int rc = ready(h);
+  if (rc) return rc;
+  const size_t need = (size_t)h->dim * h->nb;
+  if (!hist || n != need) return VEGAS_EINVAL;
+  for (size_t i = 0; i < need; ++i)
+    if (!(hist[i] >= 0.0) || !std::isfinite(hist[i])) return VEGAS_EINVAL;
+  DeviceGuard dg(h->device);
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  std::memcpy(h->pinned, hist, need * sizeof(double));
+  VEGAS_TRY(h, hipMemcpyAsync(h->g.hist, h->pinned, need * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  h->hist_valid = true;
+  return VEGAS_OK;
+}
+
+int vegas_get_iteration(vegas_h h, uint32_t* t) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!t) return VEGAS_EINVAL;
+  *t = h->t;
+  return VEGAS_OK;
+}
+
+int vegas_set_iteration(vegas_h h, uint32_t t) {
+  int rc = ready(h);
+  if (rc) return rc;
+  DeviceGuard dg(h->device);
+  VEGAS_TRY(h, launch_set_t(h->g, t, h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  h->t = t;
+  return VEGAS_OK;
+}
+
+int vegas_nonfinite(vegas_h h, int64_t* count) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!count) return VEGAS_EINVAL;
+  *count = h->last_bad;
+  return VEGAS_OK;
+}
+
+int vegas_dump_weights(vegas_h h, int integrand_id, uint64_t seed, uint64_t first, int64_t count,
+                       double* w_out) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (count < 0 || count > (int64_t(1) << 26) || (count > 0 && !w_out)) return VEGAS_EINVAL;
+  IntegrandArgs P;
+  rc = integrand_args(h, integrand_id, &P);
+  if (rc) return rc;
+  if (count == 0) return VEGAS_OK;
+  DeviceGuard dg(h->device);
+  if (h->dump_n < (size_t)count) {
+    if (h->dump_buf) VEGAS_TRY(h, hipFree(h->dump_buf));
+    h->dump_buf = nullptr;
+    h->dump_n = 0;
+    VEGAS_TRY(h, hipMalloc(reinterpret_cast<void**>(&h->dump_buf), sizeof(double) * count));
+    h->dump_n = (size_t)count;
+  }
+  IterLaunch L;
+  L.fid = integrand_id;
+  L.prec = h->prec;
+  L.seed = seed;
+  L.first = first;
+  L.count = count;
+  L.w_out = h->dump_buf;
+  VEGAS_TRY(h, launch_dump(h->g, L, P, h->stream));
+  VEGAS_TRY(h, hipMemcpyAsync(w_out, h->dump_buf, sizeof(double) * count, hipMemcpyDeviceToHost,
+                              h->stream));
+  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
+  return VEGAS_OK;
+}
+
+int vegas_set_launch(vegas_h h, int max_blocks, int threads) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (max_blocks < 0 || max_blocks > kMaxBlocks) return VEGAS_EINVAL;
+  if (threads == 0) threads = 256;
+  if (threads != 64 && threads != 128 && threads != 256) return VEGAS_EINVAL;
+  h->max_blocks = max_blocks;
+  h->threads = threads;
+  return VEGAS_OK;
+}
+
+int vegas_timing(vegas_h h, int enable, int reset, double* iterate_ms, int64_t* n_launches) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (iterate_ms) *iterate_ms = h->time_ms;
+  if (n_launches) *n_launches = h->n_timed;
+  if (reset || (enable != 0) != h->timing) {
+    h->time_ms = 0.0;
+    h->n_timed = 0;
+  }
+  h->timing = enable != 0;
+  return VEGAS_OK;
+}
+
+}  // extern "C"

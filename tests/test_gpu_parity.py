@@ -1,0 +1,278 @@
+"""Parity of the HIP path with the FP64 CPU oracle, through the C interface.
+
+FP64 mode must match the oracle within 1e-12 relative (per-event weights,
+(I, sigma), histogram, refined grid, whole runs). FP32-eval mode must stay
+within 0.1 sigma of the oracle per iteration. Inputs are seeded and synthetic
+(paper_2010_09341_amd.workloads); nothing here feeds a GPU result into the
+oracle.
+"""
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+from paper_2010_09341_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def vg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    from paper_2010_09341_amd import vegas
+    vegas.lib()
+    return vegas
+
+
+def _close(a, b, rtol=RTOL, atol=0.0):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.all(np.abs(a - b) <= rtol * np.abs(b) + atol)
+
+
+def _handle(vg, dim, nb, fid=None, params=None, prec=W.FP64, grid=None, t=0):
+    h = vg.vegas_create(dim, nb)
+    if fid is not None and params is not None:
+        vg.vegas_set_params(h, fid, params)
+    vg.vegas_set_precision(h, prec)
+    if grid is not None:
+        vg.vegas_set_grid(h, grid)
+    if t:
+        vg.vegas_set_iteration(h, t)
+    return h
+
+
+CASES = [
+    # (name, dim, nb, fid, params)
+    ("const3", 3, 7, W.F_CONST, None),
+    ("sum10", 10, 20, W.F_SUM, None),
+    ("gauss8", 8, 50, W.F_GAUSS, [0.1]),
+    ("gauss5c", 5, 37, W.F_GAUSS, [0.2, 0.3, 0.45, 0.5, 0.6, 0.7]),
+    ("lo_toy", 4, 100, W.F_LO_TOY, [13000.0, 91.19, 2.5, 20.0]),
+    ("rambo", 16, 50, W.F_RAMBO24, [1000.0, 0.01, 0.0]),
+    ("rambo_ps", 16, 50, W.F_RAMBO24, [1000.0, 0.01, 1.0]),
+    ("bw5", 5, 30, W.F_BW_FLAT, [0.42, 0.03]),
+]
+
+
+@pytest.mark.parametrize("name,dim,nb,fid,params", CASES, ids=[c[0] for c in CASES])
+def test_weights_fp64(vg, orc, name, dim, nb, fid, params):
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    grid = W.random_grid(rng, dim, nb)
+    seed = (5 << 32) | 17
+    t = 3
+    first = 2**32 - 1500  # crosses the 32-bit boundary of the event index
+    count = 3001
+    h = _handle(vg, dim, nb, fid, params, W.FP64, grid, t)
+    w_gpu = vg.vegas_dump_weights(h, fid, seed, first, count)
+    w_ref = orc.weights(grid, fid, params, seed, t, first, count)
+    scale = np.max(np.abs(w_ref))
+    assert _close(w_gpu, w_ref, atol=1e-300 + 1e-15 * scale), \
+        np.max(np.abs(w_gpu - w_ref) / (np.abs(w_ref) + 1e-300))
+    if fid not in (W.F_CONST, W.F_RAMBO24):
+        assert np.unique(w_gpu).size > count // 2
+
+
+@pytest.mark.parametrize("name,dim,nb,fid,params", CASES, ids=[c[0] for c in CASES])
+def test_iterate_fp64(vg, orc, name, dim, nb, fid, params):
+    rng = np.random.default_rng(1 + zlib.crc32(name.encode()))
+    grid = W.random_grid(rng, dim, nb)
+    n = 100_003  # several workgroups and a ragged tail
+    seed, t = 11, 2
+    h = _handle(vg, dim, nb, fid, params, W.FP64, grid, t)
+    I, s = vg.vegas_iterate(h, fid, n, seed)
+    I_r, s_r, h_r, bad_r = orc.iterate(grid, fid, params, n, seed, t)
+    assert vg.vegas_nonfinite(h) == bad_r == 0
+    assert _close(I, I_r), (I, I_r)
+    if fid == W.F_CONST or (fid == W.F_RAMBO24 and params[2] == 1.0):
+        # constant weight on any grid only through the Jacobian; compare sigma loosely
+        assert _close(s, s_r, rtol=1e-6, atol=1e-12 * abs(I_r))
+    else:
+        assert _close(s, s_r, rtol=1e-10), (s, s_r)
+    hist = vg.vegas_get_hist(h)
+    assert _close(hist, h_r, rtol=1e-12, atol=1e-13 * h_r.max())
+    assert vg.vegas_get_iteration(h) == t + 1
+
+
+SHAPES = [(1, 2, 2), (1, 512, 1000), (5, 37, 99_991), (13, 17, 77_777), (32, 64, 50_001),
+          (16, 128, 40_000), (4, 512, 65_536)]
+
+
+@pytest.mark.parametrize("dim,nb,n", SHAPES)
+def test_iterate_shapes_fp64(vg, orc, dim, nb, n):
+    """Gaussian on random grids across shapes: the minimum (1 dim, 2 bins,
+    2 events), the bin maximum, dimensions that leave partial Philox blocks,
+    32 dimensions, and the cell maximum dim * nb = 2048."""
+    rng = np.random.default_rng(dim * 1000 + nb)
+    grid = W.random_grid(rng, dim, nb)
+    params = [0.3] + list(rng.uniform(0.3, 0.7, dim))
+    h = _handle(vg, dim, nb, W.F_GAUSS, params, W.FP64, grid)
+    I, s = vg.vegas_iterate(h, W.F_GAUSS, n, 123)
+    I_r, s_r, h_r, _ = orc.iterate(grid, W.F_GAUSS, params, n, 123, 0)
+    assert _close(I, I_r), (I, I_r)
+    assert _close(s, s_r, rtol=1e-10)
+    assert _close(vg.vegas_get_hist(h), h_r, rtol=1e-12, atol=1e-14 * h_r.max())
+
+
+@pytest.mark.parametrize("alpha,zeros", [(1.5, 0.0), (1.5, 0.3), (0.0, 0.0), (0.5, 0.1),
+                                         (2.0, 0.6)])
+@pytest.mark.parametrize("dim,nb", [(1, 2), (3, 50), (8, 100), (2, 512)])
+def test_refine_fp64(vg, orc, alpha, zeros, dim, nb):
+    rng = np.random.default_rng(int(alpha * 7) + nb + dim)
+    grid = W.random_grid(rng, dim, nb)
+    hist = W.random_hist(rng, dim, nb, zeros=zeros)
+    if dim > 1:
+        hist[-1] = 0.0  # an empty dimension keeps its edges
+    h = _handle(vg, dim, nb, grid=grid)
+    vg.vegas_set_hist(h, hist)
+    vg.vegas_refine(h, alpha)
+    got = vg.vegas_get_grid(h)
+    ref = orc.refine(grid, hist, alpha)
+    assert np.all(got[:, 0] == 0.0) and np.all(got[:, -1] == 1.0)
+    assert np.all(np.diff(got, axis=1) > 0)
+    assert np.max(np.abs(got - ref)) < 1e-13
+
+
+def test_run_gauss4d_fp64(vg, orc):
+    """The 4-D Gaussian workload (5 x 1e5 events, 50 bins, alpha 1.5, seed 0):
+    every iteration and the final grid match the oracle."""
+    wl = W.WORKLOADS["gauss4d"]
+    h = _handle(vg, wl.dim, wl.nb, wl.fid, wl.params)
+    I_t, s_t = vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+    I_r, s_r, e_r, _ = orc.run(wl.dim, wl.nb, wl.fid, wl.params, wl.n_events, wl.seed,
+                               wl.n_iter, wl.alpha)
+    assert _close(I_t, I_r), np.max(np.abs(I_t - I_r) / I_r)
+    assert _close(s_t, s_r, rtol=1e-10)
+    assert np.max(np.abs(vg.vegas_get_grid(h) - e_r)) < 1e-12
+    I, s, chi2 = vg.vegas_result(h)
+    I_o, s_o, c_o = orc.combine(I_r, s_r)
+    assert _close([I, s], [I_o, s_o], rtol=1e-11)
+    assert abs(I - 0.99999999999385016) < 4 * s
+
+
+def test_iterate_equals_run(vg):
+    """vegas_iterate + vegas_refine step by step equals one vegas_run."""
+    h1 = _handle(vg, 6, 40, W.F_GAUSS, [0.15])
+    h2 = _handle(vg, 6, 40, W.F_GAUSS, [0.15])
+    I_run, s_run = vg.vegas_run(h1, W.F_GAUSS, 50_000, 3, 4, 1.5)
+    for i in range(4):
+        I, s = vg.vegas_iterate(h2, W.F_GAUSS, 50_000, 3)
+        assert _close(I, I_run[i], rtol=1e-14)
+        if i < 3:
+            vg.vegas_refine(h2, 1.5)
+    assert np.max(np.abs(vg.vegas_get_grid(h1) - vg.vegas_get_grid(h2))) < 1e-14
+
+
+@pytest.mark.parametrize("name", ["lo_toy", "rambo24"])
+def test_run_physics_fp64(vg, orc, name):
+    """The LO toy and RAMBO workloads at reduced event counts, FP64."""
+    wl = W.WORKLOADS[name]
+    n = 200_000 if name == "lo_toy" else 50_000
+    h = _handle(vg, wl.dim, wl.nb, wl.fid, wl.params)
+    I_t, s_t = vg.vegas_run(h, wl.fid, n, wl.seed, 4, wl.alpha)
+    I_r, s_r, e_r, _ = orc.run(wl.dim, wl.nb, wl.fid, wl.params, n, wl.seed, 4, wl.alpha)
+    assert _close(I_t, I_r, rtol=1e-11), np.max(np.abs(I_t - I_r) / I_r)
+    assert _close(s_t, s_r, rtol=1e-9)
+
+
+@pytest.mark.parametrize("name,dim,nb,fid,params", CASES, ids=[c[0] for c in CASES])
+def test_iterate_fp32_eval(vg, orc, name, dim, nb, fid, params):
+    """FP32-eval: within 0.1 sigma of the FP64 oracle on the same events, and
+    sigma within 1%."""
+    rng = np.random.default_rng(2 + zlib.crc32(name.encode()))
+    grid = W.random_grid(rng, dim, nb, spread=1.5)
+    n = 200_000
+    h = _handle(vg, dim, nb, fid, params, W.FP32_EVAL, grid, 1)
+    I, s = vg.vegas_iterate(h, fid, n, 77)
+    I_r, s_r, _, _ = orc.iterate(grid, fid, params, n, 77, 1)
+    if s_r > 1e-9 * abs(I_r):
+        assert abs(I - I_r) < 0.1 * s_r, (I, I_r, s_r)
+        assert abs(s / s_r - 1) < 1e-2
+    else:
+        assert abs(I - I_r) < 1e-6 * abs(I_r)
+
+
+def test_fp32_eval_gauss_tails(vg, orc):
+    """Narrow 12-D Gaussian (a = 0.05): the outer bins collect w^2 of order
+    1e-128, far below the binary32 range; the binary64 weight formed from the
+    binary32 log2-sum keeps every bin populated where the oracle's is."""
+    dim, nb = 12, 50
+    params = [0.05] + [0.5] * dim
+    h = _handle(vg, dim, nb, W.F_GAUSS, params, W.FP32_EVAL)
+    vg.vegas_iterate(h, W.F_GAUSS, 300_000, 5)
+    hist = vg.vegas_get_hist(h)
+    _, _, h_r, _ = orc.iterate(orc.uniform_grid(dim, nb), W.F_GAUSS, params, 300_000, 5, 0)
+    assert np.all(h_r > 0)
+    assert np.all(hist > 0)
+    assert _close(hist.sum(axis=1), h_r.sum(axis=1), rtol=1e-3)
+
+
+def test_nonfinite_counted(vg, orc):
+    """LO toy without its cut on a grid whose first bin is 1e-300 wide: the
+    weights near x1 = 0 overflow; both sides count the same events."""
+    e = np.tile(np.linspace(0, 1, 9), (4, 1))
+    e[:, 1] = 1e-300
+    params = [13000.0, 91.19, 2.5, -1.0]
+    h = _handle(vg, 4, 8, W.F_LO_TOY, params, W.FP64, e)
+    I, s = vg.vegas_iterate(h, W.F_LO_TOY, 40_000, 0)
+    _, _, _, bad_r = orc.iterate(e, W.F_LO_TOY, params, 40_000, 0, 0)
+    assert bad_r > 0
+    assert vg.vegas_nonfinite(h) == bad_r
+    assert math.isfinite(I) and math.isfinite(s)
+    assert np.all(np.isfinite(vg.vegas_get_hist(h)))
+
+
+def test_launch_shape_independence(vg):
+    """The estimate does not depend on the launch shape beyond rounding; the
+    same shape gives bitwise the same estimate."""
+    grid = W.random_grid(np.random.default_rng(3), 7, 33)
+    res = []
+    for blocks, threads in ((0, 0), (0, 0), (7, 64), (1, 256), (300, 128)):
+        h = _handle(vg, 7, 33, W.F_SUM, None, W.FP64, grid)
+        vg.vegas_set_launch(h, blocks, threads)
+        res.append(vg.vegas_iterate(h, W.F_SUM, 123_457, 9))
+    assert res[0] == res[1]
+    for I, s in res[2:]:
+        assert _close(I, res[0][0], rtol=1e-14)
+
+
+def test_own_memory_matches_torch_memory(vg):
+    h1 = vg.vegas_create(5, 20, torch_memory=False)
+    h2 = vg.vegas_create(5, 20, torch_memory=True)
+    for h in (h1, h2):
+        vg.vegas_set_params(h, W.F_GAUSS, [0.2])
+    r1 = vg.vegas_run(h1, W.F_GAUSS, 30_000, 1, 3, 1.5)
+    r2 = vg.vegas_run(h2, W.F_GAUSS, 30_000, 1, 3, 1.5)
+    assert np.allclose(r1[0], r2[0], rtol=1e-14, atol=0)
+
+
+def test_state_machine(vg):
+    h = vg.vegas_create(3, 10)
+    with pytest.raises(vg.VegasError) as e:
+        vg.vegas_refine(h, 1.5)
+    assert e.value.code == vg.VEGAS_ESTATE
+    with pytest.raises(vg.VegasError) as e:
+        vg.vegas_result(h)
+    assert e.value.code == vg.VEGAS_ESTATE
+    with pytest.raises(vg.VegasError) as e:
+        vg.vegas_iterate(h, W.F_LO_TOY, 100, 0)  # the LO toy needs 4 dimensions
+    assert e.value.code == vg.VEGAS_EINVAL
+    with pytest.raises(vg.VegasError):
+        vg.vegas_iterate(h, W.F_CONST, 1, 0)
+    assert vg.vegas_get_iteration(h) == 0
+    vg.vegas_iterate(h, W.F_SUM, 1000, 0)
+    vg.vegas_refine(h, 1.5)
+    with pytest.raises(vg.VegasError):
+        vg.vegas_refine(h, 1.5)
+    vg.vegas_reset(h)
+    assert vg.vegas_get_iteration(h) == 0
+    assert np.allclose(vg.vegas_get_grid(h), np.tile(np.arange(11) / 10, (3, 1)), atol=1e-16)
+    bad = np.tile(np.linspace(0, 1, 11), (3, 1))
+    bad[1, 4] = bad[1, 5]
+    with pytest.raises(vg.VegasError):
+        vg.vegas_set_grid(h, bad)
