@@ -1,0 +1,240 @@
+"""Benchmark: Vegas events/s on one MI355X, FP32-eval at matched sigma against
+FP64, with per-iteration latency percentiles, the iteration kernel's ALU
+roofline, and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gauss8d]
+                    [--no-cpu] [--no-serving]
+
+One step is one whole integration of the workload: grid reset to uniform,
+n_iter iterations (draw, map, integrand, moments, histogram) with a grid
+refinement after each but the last, and the inverse-variance combination.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes issue one full-rate VALU operation per lane per
+# clock at 2.4 GHz. A quarter-rate operation (64-bit integer multiply-add,
+# binary32 transcendentals) occupies four such lane slots.
+PEAK_VALU_SLOTS = 256 * 64 * 2.4e9  # 3.93e13 lane slots/s
+PEAK_FP32_FLOPS = 157.3e12
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def alg_slots_per_event(dim: int, nblk: int, prec: int, fid: int) -> float:
+    """Algorithmic VALU lane slots per event for the Gaussian workloads.
+
+    Philox4x32-10: 10 rounds x (2 mul 32x32->64 at 4 slots + 4 xor) = 120.
+    Map per dimension: mul 32x32->64 (4) + fraction (2) + fma (1) + Jacobian
+    accumulation (1, FP32 log-sum / 2 FP64 multiplies) + LDS address (1).
+    Gaussian per dimension: subtract + fma (2). Weight: FP32 fma, floor,
+    subtract, exp2 (4), convert, ldexp, multiply (10); FP64 exp ~ 24.
+    Moments: add, fma, add (3). Histogram: address per dimension (1).
+    """
+    if fid != 2:
+        return float("nan")
+    philox = nblk * 120
+    if prec == 1:
+        per_dim = 4 + 2 + 1 + 1 + 1 + 2 + 1
+        tail = 10
+    else:
+        per_dim = 4 + 2 + 1 + 2 + 1 + 2 + 1
+        tail = 24 + 2
+    return philox + dim * per_dim + tail + 3
+
+
+def fp32_flops_per_event(dim: int) -> float:
+    """Binary32 floating-point operations of the FP32-eval Gaussian per event
+    (fma = 2): map fma (2) + log-sum add (1) + subtract and fma (3) per
+    dimension, and the weight's fma, subtract, exp2 (3)."""
+    return dim * 6 + 3
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gauss8d")
+    ap.add_argument("--latency-reps", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2010_09341_amd import vegas as vg
+    from paper_2010_09341_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wl = W.WORKLOADS[args.workload]
+    events_per_step = wl.n_events * wl.n_iter
+    nblk = (wl.dim + 3) // 4
+
+    def make(prec):
+        h = vg.vegas_create(wl.dim, wl.nb)
+        vg.vegas_set_params(h, wl.fid, wl.params)
+        vg.vegas_set_precision(h, prec)
+        return h
+
+    def step(h):
+        vg.vegas_reset(h)
+        I_t, s_t = vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+        return I_t, s_t, vg.vegas_result(h)
+
+    results = {}
+    for prec in (W.FP32_EVAL, W.FP64):
+        log(f"{wl.name} prec={prec}: {args.warmup} warmup + {args.steps} timed steps")
+        h = make(prec)
+        for _ in range(args.warmup):
+            step(h)
+        torch.cuda.synchronize()
+        vg.vegas_timing(h, True, True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            I_t, s_t, comb = step(h)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        k_ms, k_n = vg.vegas_timing(h, False)
+        # per-iteration latency: one synchronous vegas_iterate (launch, kernels,
+        # 32-byte result copy, synchronisation) on the adapted grid
+        lat = []
+        for i in range(args.latency_reps):
+            a = time.perf_counter()
+            vg.vegas_iterate(h, wl.fid, wl.n_events, wl.seed)
+            lat.append(time.perf_counter() - a)
+        log(f"prec={prec}: {dt / args.steps * 1e3:.3f} ms/step, latency p50 "
+            f"{pct(lat, 50) * 1e3:.3f} ms")
+        results[prec] = dict(dt=dt, I_t=I_t, s_t=s_t, comb=comb, k_ms=k_ms, k_n=k_n, lat=lat)
+        del h
+
+    r32, r64 = results[W.FP32_EVAL], results[W.FP64]
+    value = events_per_step * args.steps / r32["dt"]
+    value64 = events_per_step * args.steps / r64["dt"]
+    I32, s32, _ = r32["comb"]
+    I64, s64, _ = r64["comb"]
+    matched = abs(s32 / s64 - 1.0) < 1e-2
+
+    # roofline of the iteration kernel (FP32-eval), from HIP events around
+    # every launch of it inside the timed steps
+    k_avg_s = r32["k_ms"] / max(r32["k_n"], 1) * 1e-3
+    slots = alg_slots_per_event(wl.dim, nblk, W.FP32_EVAL, wl.fid)
+    achieved = slots * wl.n_events / k_avg_s
+    k64_avg_s = r64["k_ms"] / max(r64["k_n"], 1) * 1e-3
+    slots64 = alg_slots_per_event(wl.dim, nblk, W.FP64, wl.fid)
+
+    out = {
+        "metric": "Vegas events/sec at matched sigma (FP32-eval vs FP64) on 1 GPU; "
+                  "p50/p99 latency",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["dt"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-eval/f64-accumulate",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: {wl.note}; Philox seed {wl.seed}, refinement alpha "
+                        f"{wl.alpha}",
+            "dim": wl.dim, "n_bins": wl.nb, "events_per_iteration": wl.n_events,
+            "iterations": wl.n_iter, "events_per_step": events_per_step,
+            "parallelism": "single GPU",
+        },
+        "matched_sigma": {"fp32_eval": {"I": I32, "sigma": s32},
+                          "fp64": {"I": I64, "sigma": s64, "events_per_s": value64,
+                                   "ms_per_step": r64["dt"] / args.steps * 1e3},
+                          "sigma_ratio": s32 / s64, "matched": matched,
+                          "fp32_minus_fp64_over_sigma": (I32 - I64) / s64,
+                          "figure_of_merit_fp32": 1.0 / (s32 ** 2 * r32["dt"] / args.steps),
+                          "figure_of_merit_fp64": 1.0 / (s64 ** 2 * r64["dt"] / args.steps)},
+        "latency_ms": {
+            "what": "one synchronous vegas_iterate of the workload's events/iteration",
+            "fp32_eval": {"p50": pct(r32["lat"], 50) * 1e3, "p99": pct(r32["lat"], 99) * 1e3},
+            "fp64": {"p50": pct(r64["lat"], 50) * 1e3, "p99": pct(r64["lat"], 99) * 1e3},
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": f"k_iterate<{nblk},gauss,fp32-eval>",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_VALU_SLOTS / 1e12,
+            "unit": "T VALU lane-slots/s",
+            "frac": achieved / PEAK_VALU_SLOTS,
+            "traffic": None,
+            "slots_per_event": slots,
+            "avg_launch_us": k_avg_s * 1e6,
+            "launches": r32["k_n"],
+            "fp32_flop_frac_of_157TF": fp32_flops_per_event(wl.dim) * wl.n_events / k_avg_s
+            / PEAK_FP32_FLOPS,
+            "fp64_kernel": {"avg_launch_us": k64_avg_s * 1e6,
+                            "frac": slots64 * wl.n_events / k64_avg_s / PEAK_VALU_SLOTS},
+        },
+    }
+    closed = W.gauss_closed_form(wl.dim, wl.params[0]) if wl.fid == W.F_GAUSS else None
+    if closed is not None:
+        out["closed_form"] = {"I": closed, "fp32_pull": (I32 - closed) / s32,
+                              "fp64_pull": (I64 - closed) / s64}
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(wl, r64["I_t"], r64["s_t"])
+    if not args.no_serving:
+        try:
+            from paper_2010_09341_amd import serving_bench
+            out["serving"] = serving_bench.run_quick()
+        except (ImportError, AttributeError):
+            pass
+    print(json.dumps(out))
+
+
+def cpu_baseline(wl, gpu_I_t, gpu_s_t):
+    """The FP64 oracle, single-threaded as written, on the first iterations of
+    the same workload (same seed): about 10-20 s of CPU work."""
+    import oracle
+    n_iter = 5 if wl.n_events >= 10_000_000 else wl.n_iter
+    n_ev = min(wl.n_events, 10_000_000)
+    t0 = time.perf_counter()
+    I_t, s_t, _, _ = oracle.run(wl.dim, wl.nb, wl.fid, wl.params, n_ev, wl.seed, n_iter,
+                                wl.alpha)
+    dt = time.perf_counter() - t0
+    res = {"value": n_ev * n_iter / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {n_iter} of {wl.n_iter} iterations of {wl.name} at "
+                     f"{n_ev:.0e} events each (FP64, seed {wl.seed}), {dt:.1f} s"}
+    if n_ev == wl.n_events:
+        rel = np.max(np.abs(np.asarray(gpu_I_t[:n_iter]) - I_t) / np.abs(I_t))
+        res["fp64_gpu_vs_oracle_max_rel_err_I_t"] = float(rel)
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -84,7 +84,10 @@ def lib():
                                   "`python -m paper_2010_09341_amd.build`")
             L = ctypes.CDLL(LIB_PATH)
             for name, args in _SIGS.items():
-                fn = getattr(L, name)
+                try:
+                    fn = getattr(L, name)
+                except AttributeError:
+                    continue  # reported by the export test; calling it raises
                 fn.argtypes = args
                 fn.restype = _c.c_int
             L.vegas_strerror.argtypes = [_c.c_int]
