@@ -94,7 +94,7 @@ extern "C" {
 #define VEGAS_MAX_DIM 32
 #define VEGAS_MAX_BINS 512
 /* dim * n_bins may not exceed this (the grid and the histogram of one block
- * are staged in 24 bytes per (dimension, bin) of LDS). */
+ * are staged in 32 bytes per (dimension, bin) of LDS, at most 64 KiB). */
 #define VEGAS_MAX_CELLS 2048
 #define VEGAS_MAX_PARAMS (1 + VEGAS_MAX_DIM)
 /* vegas_run may queue at most this many iterations per call. */

@@ -20,6 +20,12 @@ LIB = os.path.join(HERE, "libvegas.so")
 
 SOURCES = [
     "vegas_kernels.hip",
+    "iter_const.hip",
+    "iter_sum.hip",
+    "iter_gauss.hip",
+    "iter_lo_toy.hip",
+    "iter_rambo24.hip",
+    "iter_bw_flat.hip",
     "vegas_runtime.cpp",
     "vegas_server.cpp",
 ]

@@ -32,8 +32,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
   for (int round = 0; round < 10; ++round) {
     const uint64_t pa = (uint64_t)c0 * 0xD2511F53u;
     const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
-    const uint32_t next0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-    const uint32_t next2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    // three-input xor (truth table 0x96) in one gfx950 v_bitop3_b32
+    const uint32_t next0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, k0, 0x96);
+    const uint32_t next2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, k1, 0x96);
     c1 = (uint32_t)pb;
     c3 = (uint32_t)pa;
     c0 = next0;
@@ -115,21 +116,22 @@ __device__ __forceinline__ double rambo24_f64(const double* x, const IntegrandAr
 }
 
 template <int FID>
-__device__ __forceinline__ double integrand_f64(const double* x, int D, const IntegrandArgs& P) {
+__device__ __forceinline__ double integrand_f64(const double* x, int DMAX, int D,
+                                                const IntegrandArgs& P) {
   if constexpr (FID == kConst) {
     return 1.0;
   } else if constexpr (FID == kSum) {
     double s = 0.0;
 #pragma unroll
     for (int d = 0; d < kMaxDim; ++d)
-      if (d < D) s += x[d];
+      if (d < DMAX && d < D) s += x[d];
     return s;
   } else if constexpr (FID == kGauss) {
     // prod_d exp(-z_d^2/a^2)/(a sqrt(pi)) = exp(-sum z_d^2 / a^2 - D ln(a sqrt(pi)))
     double acc = 0.0;
 #pragma unroll
     for (int d = 0; d < kMaxDim; ++d)
-      if (d < D) {
+      if (d < DMAX && d < D) {
         const double z = x[d] - P.c64[d];
         acc += z * z;
       }
@@ -217,21 +219,22 @@ __device__ __forceinline__ float rambo24_f32(const float* x, const IntegrandArgs
 }
 
 template <int FID>
-__device__ __forceinline__ F32Val integrand_f32(const float* x, int D, const IntegrandArgs& P) {
+__device__ __forceinline__ F32Val integrand_f32(const float* x, int DMAX, int D,
+                                                const IntegrandArgs& P) {
   F32Val r{1.f, 0.f};
   if constexpr (FID == kConst) {
   } else if constexpr (FID == kSum) {
     float s = 0.f;
 #pragma unroll
     for (int d = 0; d < kMaxDim; ++d)
-      if (d < D) s += x[d];
+      if (d < DMAX && d < D) s += x[d];
     r.f = s;
   } else if constexpr (FID == kGauss) {
     // log2 f = -(log2 e / a^2) sum z^2 - D log2(a sqrt(pi))
     float acc = 0.f;
 #pragma unroll
     for (int d = 0; d < kMaxDim; ++d)
-      if (d < D) {
+      if (d < DMAX && d < D) {
         const float z = x[d] - P.c32[d];
         acc = fmaf(z, z, acc);
       }
@@ -257,71 +260,103 @@ __device__ __forceinline__ F32Val integrand_f32(const float* x, int D, const Int
 }
 
 // ---------------------------------------------------------------------------
-// One event: draw, map, evaluate. Returns w = f(x) * J in binary64 and the
-// bin index of every dimension in bins[] (offset by d * nb, i.e. the LDS
-// histogram cell).
+// LDS cell of (dimension d, bin k): the grid record and the bin's w^2 sum,
+// 32 bytes at byte offset (d * nb + k) * 32 of the workgroup's LDS, so the
+// record is one 16-byte-aligned LDS read and the sum one LDS atomic.
 // ---------------------------------------------------------------------------
-template <int NBLK, int FID, int PREC>
+struct alignas(16) Cell64 {
+  double e, w;  // e_k, e_{k+1} - e_k
+  double h;     // sum of w^2
+  double pad;
+};
+struct alignas(16) Cell32 {
+  float e, w, l2j, pad;  // binary32 record (see Rec32)
+  double h;
+  double pad2;
+};
+static_assert(sizeof(Cell64) == 32 && sizeof(Cell32) == 32, "32-byte LDS cells");
+constexpr int kCellBytes = 32;
+constexpr int kCellHistOffset = 16;
+
+// Dimension count: D_T > 0 is the exact count known at compile time; D_T < 0
+// means at most -D_T dimensions with the actual count D given at run time.
+template <int D_T>
+struct Dims {
+  static constexpr int kMax = D_T > 0 ? D_T : -D_T;
+  static constexpr int kBlocks = (kMax + 3) / 4;
+  __device__ static constexpr bool on(int d, int D) { return D_T > 0 ? d < D_T : d < D; }
+};
+
+// ---------------------------------------------------------------------------
+// One event: draw, map, evaluate. Returns w = f(x) * J in binary64 and, in
+// cell[d], the LDS byte offset of the cell that dimension d fell into.
+// ---------------------------------------------------------------------------
+template <int D_T, int FID, int PREC>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
-                                               int D, uint32_t nb, const void* srec,
-                                               const IntegrandArgs& P, int* bins) {
-  constexpr int DMAX = 4 * NBLK;
+                                               int D, uint32_t nb, double nb_pow_d,
+                                               const unsigned char* lds, const IntegrandArgs& P,
+                                               uint32_t* cell) {
+  using Dm = Dims<D_T>;
   const uint32_t n_lo = (uint32_t)n, n_hi = (uint32_t)(n >> 32);
+  const uint32_t row = nb * (uint32_t)kCellBytes;
   if constexpr (PREC == kFp64) {
-    const Rec64* rec = static_cast<const Rec64*>(srec);
-    double x[DMAX];
+    double x[Dm::kMax];
     double jac = 1.0;
-    const double nbf = (double)nb;
 #pragma unroll
-    for (int j = 0; j < NBLK; ++j) {
-      if (4 * j < D) {
+    for (int j = 0; j < Dm::kBlocks; ++j) {
+      if (Dm::on(4 * j, D)) {
         const Words4 r = philox4x32_10(n_lo, n_hi, t, (uint32_t)j, k0, k1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int d = 4 * j + i;
-          if (d < D) {
+          if (d < Dm::kMax && Dm::on(d, D)) {
             const uint64_t prod = (uint64_t)r.v[i] * nb;
-            const int k = (int)(prod >> 32);
+            const uint32_t k = (uint32_t)(prod >> 32);
             const uint32_t rem = (uint32_t)prod;
             // (rem + 1/2) 2^-32, exact in binary64
             const double frac = fma((double)rem, 0x1p-32, 0x1p-33);
-            const int cell = d * (int)nb + k;
-            const Rec64 g = rec[cell];
-            x[d] = fma(frac, g.w, g.e);
-            jac *= nbf * g.w;
-            bins[d] = cell;
+            const uint32_t off = (k << 5) + (uint32_t)d * row;
+            const Cell64* c =
+                static_cast<const Cell64*>(__builtin_assume_aligned(lds + off, 16));
+            x[d] = fma(frac, c->w, c->e);
+            jac *= c->w;
+            cell[d] = off;
           }
         }
       }
     }
-    return integrand_f64<FID>(x, D, P) * jac;
+    // J = prod_d nb * w_d, with nb^D applied once
+    return integrand_f64<FID>(x, Dm::kMax, D_T > 0 ? D_T : D, P) * (jac * nb_pow_d);
   } else {
-    const Rec32* rec = static_cast<const Rec32*>(srec);
-    float x[DMAX];
+    float x[Dm::kMax];
     float l2j = 0.f;
 #pragma unroll
-    for (int j = 0; j < NBLK; ++j) {
-      if (4 * j < D) {
+    for (int j = 0; j < Dm::kBlocks; ++j) {
+      if (Dm::on(4 * j, D)) {
         const Words4 r = philox4x32_10(n_lo, n_hi, t, (uint32_t)j, k0, k1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int d = 4 * j + i;
-          if (d < D) {
+          if (d < Dm::kMax && Dm::on(d, D)) {
             const uint64_t prod = (uint64_t)r.v[i] * nb;
-            const int k = (int)(prod >> 32);
+            const uint32_t k = (uint32_t)(prod >> 32);
             const uint32_t rem = (uint32_t)prod;
-            // centre of the 2^-23 cell: ((rem >> 9) + 1/2) 2^-23, exact in binary32
-            const float frac = (float)((rem >> 8) | 1u) * 0x1p-24f;
-            const int cell = d * (int)nb + k;
-            const Rec32 g = rec[cell];
-            x[d] = fmaf(frac, g.w, g.e);
-            l2j += g.l2j;
-            bins[d] = cell;
+            // 1 + (rem >> 9) 2^-23 by placing the bits under the exponent of
+            // 1.0, then minus (1 - 2^-24): the centre ((rem >> 9) + 1/2) 2^-23
+            // of a 2^-23 cell, exact in binary32
+            const float frac =
+                __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u)) - 0x1.fffffep-1f;
+            const uint32_t off = (k << 5) + (uint32_t)d * row;
+            const Cell32* c =
+                static_cast<const Cell32*>(__builtin_assume_aligned(lds + off, 16));
+            x[d] = fmaf(frac, c->w, c->e);
+            l2j += c->l2j;
+            cell[d] = off;
           }
         }
       }
     }
-    const F32Val v = integrand_f32<FID>(x, D, P);
+    const F32Val v = integrand_f32<FID>(x, Dm::kMax, D_T > 0 ? D_T : D, P);
     // w = f * 2^(log2 J + log2 f), the power split into a binary32 mantissa
     // in [1, 2) and an integer exponent applied in binary64.
     const float l2 = l2j + v.log2f;

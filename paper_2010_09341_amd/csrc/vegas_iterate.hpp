@@ -1,0 +1,177 @@
+// vegas_iterate.hpp — the iteration kernel template: draw (Philox4x32-10 in
+// registers) -> grid map (records in LDS) -> integrand -> sum w, sum w^2
+// (binary64, wave shuffles + LDS) -> w^2 histogram (LDS-private binary64
+// atomics, flushed with global binary64 atomics into one of 8 copies chosen by
+// workgroup index, i.e. by XCD under round-robin dispatch).
+//
+// Each integrand's instantiations live in their own translation unit
+// (iter_*.hip) so they compile in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vegas_device.hpp"
+
+namespace vegas {
+
+struct IterArgsDev {
+  const uint32_t* t;
+  const void* rec;
+  double* copies;
+  double* partials;
+  double* w_out;
+  uint64_t n_events;  // events of the iteration (dump: number of events to dump)
+  uint64_t first;     // dump: index of the first event
+  double nb_pow_d;    // nb^D, the constant factor of the Jacobian
+  uint32_t seed_lo, seed_hi;
+  int dim;
+  uint32_t nb;
+};
+
+constexpr int kIterThreadsMax = 256;
+
+template <int D_T, int FID, int PREC, bool DUMP>
+__global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, IntegrandArgs P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using Dm = Dims<D_T>;
+  const int cells = a.dim * (int)a.nb;
+  if constexpr (PREC == kFp64) {
+    const Rec64* g = static_cast<const Rec64*>(a.rec);
+    Cell64* c = reinterpret_cast<Cell64*>(smem);
+    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+      const Rec64 r = g[i];
+      c[i].e = r.e;
+      c[i].w = r.w;
+      c[i].h = 0.0;
+      c[i].pad = 0.0;
+    }
+  } else {
+    const Rec32* g = static_cast<const Rec32*>(a.rec);
+    Cell32* c = reinterpret_cast<Cell32*>(smem);
+    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+      const Rec32 r = g[i];
+      c[i].e = r.e;
+      c[i].w = r.w;
+      c[i].l2j = r.l2j;
+      c[i].pad = 0.f;
+      c[i].h = 0.0;
+      c[i].pad2 = 0.0;
+    }
+  }
+  __syncthreads();
+
+  const uint32_t t = *a.t;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t cell[Dm::kMax];
+
+  if constexpr (DUMP) {
+    for (; n < a.n_events; n += stride)
+      a.w_out[n] = event_weight<D_T, FID, PREC>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
+                                                a.nb, a.nb_pow_d, smem, P, cell);
+    return;
+  } else {
+    double s1 = 0.0, s2 = 0.0;
+    uint32_t bad = 0;
+    for (; n < a.n_events; n += stride) {
+      double w = event_weight<D_T, FID, PREC>(n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
+                                              a.nb_pow_d, smem, P, cell);
+      if (!__builtin_isfinite(w)) {
+        ++bad;
+        w = 0.0;
+      }
+      const double w2 = w * w;
+      s1 += w;
+      s2 += w2;
+#pragma unroll
+      for (int d = 0; d < Dm::kMax; ++d)
+        if (Dm::on(d, a.dim))
+          __hip_atomic_fetch_add(
+              static_cast<double*>(__builtin_assume_aligned(smem + cell[d] + kCellHistOffset, 16)), w2,
+              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
+    __shared__ double red[3][kIterThreadsMax / 64];
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    bad = wave_sum_u32(bad);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+      red[0][wid] = s1;
+      red[1][wid] = s2;
+      red[2][wid] = (double)bad;
+    }
+    __syncthreads();  // also orders every LDS histogram update before the flush
+    if (threadIdx.x == 0) {
+      double a1 = 0.0, a2 = 0.0, ab = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        a1 += red[0][w];
+        a2 += red[1][w];
+        ab += red[2][w];
+      }
+      double* p = a.partials + 4 * (size_t)blockIdx.x;
+      p[0] = a1;
+      p[1] = a2;
+      p[2] = ab;
+      p[3] = 0.0;
+    }
+    double* dst = a.copies + (size_t)(blockIdx.x % kHistCopies) * cells;
+    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+      const double v = *reinterpret_cast<const double*>(smem + i * kCellBytes + kCellHistOffset);
+      if (v != 0.0)
+        __hip_atomic_fetch_add(&dst[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Kernel of one integrand for `dim` dimensions: exact dimension counts up to
+// 16, and 20/24/28/32 with the count given at run time above that.
+template <int FID, int PREC, bool DUMP>
+const void* pick_dims(int dim) {
+  if constexpr (FID == kLoToy) {
+    return dim == 4 ? (const void*)k_iterate<4, FID, PREC, DUMP> : nullptr;
+  } else if constexpr (FID == kRambo24) {
+    return dim == 16 ? (const void*)k_iterate<16, FID, PREC, DUMP> : nullptr;
+  } else {
+    switch (dim) {
+      case 1: return (const void*)k_iterate<1, FID, PREC, DUMP>;
+      case 2: return (const void*)k_iterate<2, FID, PREC, DUMP>;
+      case 3: return (const void*)k_iterate<3, FID, PREC, DUMP>;
+      case 4: return (const void*)k_iterate<4, FID, PREC, DUMP>;
+      case 5: return (const void*)k_iterate<5, FID, PREC, DUMP>;
+      case 6: return (const void*)k_iterate<6, FID, PREC, DUMP>;
+      case 7: return (const void*)k_iterate<7, FID, PREC, DUMP>;
+      case 8: return (const void*)k_iterate<8, FID, PREC, DUMP>;
+      case 9: return (const void*)k_iterate<9, FID, PREC, DUMP>;
+      case 10: return (const void*)k_iterate<10, FID, PREC, DUMP>;
+      case 11: return (const void*)k_iterate<11, FID, PREC, DUMP>;
+      case 12: return (const void*)k_iterate<12, FID, PREC, DUMP>;
+      case 13: return (const void*)k_iterate<13, FID, PREC, DUMP>;
+      case 14: return (const void*)k_iterate<14, FID, PREC, DUMP>;
+      case 15: return (const void*)k_iterate<15, FID, PREC, DUMP>;
+      case 16: return (const void*)k_iterate<16, FID, PREC, DUMP>;
+      default: break;
+    }
+    if (dim >= 17 && dim <= 20) return (const void*)k_iterate<-20, FID, PREC, DUMP>;
+    if (dim >= 21 && dim <= 24) return (const void*)k_iterate<-24, FID, PREC, DUMP>;
+    if (dim >= 25 && dim <= 28) return (const void*)k_iterate<-28, FID, PREC, DUMP>;
+    if (dim >= 29 && dim <= 32) return (const void*)k_iterate<-32, FID, PREC, DUMP>;
+    return nullptr;
+  }
+}
+
+template <int FID>
+const void* pick_integrand(int prec, int dim, bool dump) {
+  if (prec == kFp64) return dump ? pick_dims<FID, kFp64, true>(dim) : pick_dims<FID, kFp64, false>(dim);
+  return dump ? pick_dims<FID, kFp32Eval, true>(dim) : pick_dims<FID, kFp32Eval, false>(dim);
+}
+
+// One per translation unit iter_*.hip.
+const void* iterate_kernel_const(int prec, int dim, bool dump);
+const void* iterate_kernel_sum(int prec, int dim, bool dump);
+const void* iterate_kernel_gauss(int prec, int dim, bool dump);
+const void* iterate_kernel_lo_toy(int prec, int dim, bool dump);
+const void* iterate_kernel_rambo24(int prec, int dim, bool dump);
+const void* iterate_kernel_bw_flat(int prec, int dim, bool dump);
+
+}  // namespace vegas

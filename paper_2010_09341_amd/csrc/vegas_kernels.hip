@@ -1,9 +1,7 @@
 // vegas_kernels.hip — the kernels of one Vegas iteration on gfx950.
 //
-//   k_iterate   draw (Philox4x32-10 in registers) -> grid map (records in LDS)
-//               -> integrand -> sum w, sum w^2 (binary64, wave shuffles + LDS)
-//               -> w^2 histogram (LDS-private binary64 atomics, flushed with
-//               global binary64 atomics into one of 8 XCD-separated copies)
+//   k_iterate   (vegas_iterate.hpp, instantiated in iter_*.hip) draw, map,
+//               integrand, moments, w^2 histogram
 //   k_finalize  fixed-order reduction of the workgroup partials into (I, sigma),
 //               and of the histogram copies into the iteration's histogram
 //   k_refine    smoothing, normalisation, compression, equal-share re-binning
@@ -19,103 +17,10 @@
 #include <type_traits>
 
 #include "vegas_device.hpp"
+#include "vegas_iterate.hpp"
 #include "vegas_launch.hpp"
 
 namespace vegas {
-
-struct IterArgsDev {
-  const uint32_t* t;
-  const void* rec;
-  double* copies;
-  double* partials;
-  double* w_out;
-  uint64_t n_events;  // events of the iteration (dump: number of events to dump)
-  uint64_t first;     // dump: index of the first event
-  uint32_t seed_lo, seed_hi;
-  int dim;
-  uint32_t nb;
-};
-
-constexpr int kIterThreadsMax = 256;
-
-template <int NBLK, int FID, int PREC, bool DUMP>
-__global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, IntegrandArgs P) {
-  using Rec = std::conditional_t<PREC == kFp64, Rec64, Rec32>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int cells = a.dim * (int)a.nb;
-  Rec* srec = reinterpret_cast<Rec*>(smem);
-  double* shist = reinterpret_cast<double*>(smem + (size_t)cells * sizeof(Rec));
-  const Rec* grec = static_cast<const Rec*>(a.rec);
-  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-    srec[i] = grec[i];
-    if constexpr (!DUMP) shist[i] = 0.0;
-  }
-  __syncthreads();
-
-  const uint32_t t = *a.t;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int bins[4 * NBLK];
-
-  if constexpr (DUMP) {
-    for (; n < a.n_events; n += stride)
-      a.w_out[n] = event_weight<NBLK, FID, PREC>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
-                                                 a.nb, srec, P, bins);
-    return;
-  } else {
-    double s1 = 0.0, s2 = 0.0;
-    uint32_t bad = 0;
-    for (; n < a.n_events; n += stride) {
-      double w = event_weight<NBLK, FID, PREC>(n, t, a.seed_lo, a.seed_hi, a.dim, a.nb, srec,
-                                               P, bins);
-      if (!__builtin_isfinite(w)) {
-        ++bad;
-        w = 0.0;
-      }
-      const double w2 = w * w;
-      s1 += w;
-      s2 += w2;
-      if (w2 != 0.0) {
-#pragma unroll
-        for (int d = 0; d < 4 * NBLK; ++d)
-          if (d < a.dim)
-            __hip_atomic_fetch_add(&shist[bins[d]], w2, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-    }
-
-    __shared__ double red[3][kIterThreadsMax / 64];
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    bad = wave_sum_u32(bad);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-      red[0][wid] = s1;
-      red[1][wid] = s2;
-      red[2][wid] = (double)bad;
-    }
-    __syncthreads();  // also orders every LDS histogram update before the flush
-    if (threadIdx.x == 0) {
-      double a1 = 0.0, a2 = 0.0, ab = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        a1 += red[0][w];
-        a2 += red[1][w];
-        ab += red[2][w];
-      }
-      double* p = a.partials + 4 * (size_t)blockIdx.x;
-      p[0] = a1;
-      p[1] = a2;
-      p[2] = ab;
-      p[3] = 0.0;
-    }
-    double* dst = a.copies + (size_t)(blockIdx.x % kHistCopies) * cells;
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-      const double v = shist[i];
-      if (v != 0.0)
-        __hip_atomic_fetch_add(&dst[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // finalize: workgroup 0 reduces the partials in a fixed order and writes
@@ -364,50 +269,20 @@ __global__ void k_set_t(uint32_t* t, uint32_t v) {
 // ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
-template <int FID, int PREC, bool DUMP>
-static const void* pick(int nblk) {
-  if constexpr (FID == kLoToy) {
-    return nblk == 1 ? (const void*)k_iterate<1, FID, PREC, DUMP> : nullptr;
-  } else if constexpr (FID == kRambo24) {
-    return nblk == 4 ? (const void*)k_iterate<4, FID, PREC, DUMP> : nullptr;
-  } else {
-    switch (nblk) {
-      case 1: return (const void*)k_iterate<1, FID, PREC, DUMP>;
-      case 2: return (const void*)k_iterate<2, FID, PREC, DUMP>;
-      case 3: return (const void*)k_iterate<3, FID, PREC, DUMP>;
-      case 4: return (const void*)k_iterate<4, FID, PREC, DUMP>;
-      case 5: return (const void*)k_iterate<5, FID, PREC, DUMP>;
-      case 6: return (const void*)k_iterate<6, FID, PREC, DUMP>;
-      case 7: return (const void*)k_iterate<7, FID, PREC, DUMP>;
-      case 8: return (const void*)k_iterate<8, FID, PREC, DUMP>;
-      default: return nullptr;
-    }
-  }
-}
-
-template <int FID>
-static const void* pick_prec(int prec, int nblk, bool dump) {
-  if (prec == kFp64) return dump ? pick<FID, kFp64, true>(nblk) : pick<FID, kFp64, false>(nblk);
-  return dump ? pick<FID, kFp32Eval, true>(nblk) : pick<FID, kFp32Eval, false>(nblk);
-}
-
 const void* iterate_kernel(int fid, int prec, int dim, bool dump) {
   if (dim < 1 || dim > kMaxDim || (prec != kFp64 && prec != kFp32Eval)) return nullptr;
-  const int nblk = (dim + 3) / 4;
   switch (fid) {
-    case kConst: return pick_prec<kConst>(prec, nblk, dump);
-    case kSum: return pick_prec<kSum>(prec, nblk, dump);
-    case kGauss: return pick_prec<kGauss>(prec, nblk, dump);
-    case kLoToy: return pick_prec<kLoToy>(prec, nblk, dump);
-    case kRambo24: return pick_prec<kRambo24>(prec, nblk, dump);
-    case kBwFlat: return pick_prec<kBwFlat>(prec, nblk, dump);
+    case kConst: return iterate_kernel_const(prec, dim, dump);
+    case kSum: return iterate_kernel_sum(prec, dim, dump);
+    case kGauss: return iterate_kernel_gauss(prec, dim, dump);
+    case kLoToy: return iterate_kernel_lo_toy(prec, dim, dump);
+    case kRambo24: return iterate_kernel_rambo24(prec, dim, dump);
+    case kBwFlat: return iterate_kernel_bw_flat(prec, dim, dump);
     default: return nullptr;
   }
 }
 
-size_t iterate_lds_bytes(int dim, int nb) {
-  return (size_t)dim * nb * (sizeof(Rec64) + sizeof(double));
-}
+size_t iterate_lds_bytes(int dim, int nb) { return (size_t)dim * nb * kCellBytes; }
 
 static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   IterArgsDev a;
@@ -422,6 +297,7 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.seed_hi = (uint32_t)(L.seed >> 32);
   a.dim = g.dim;
   a.nb = (uint32_t)g.nb;
+  a.nb_pow_d = pow((double)g.nb, (double)g.dim);
   return a;
 }
 
