@@ -26,6 +26,7 @@ SOURCES = [
     "iter_lo_toy.hip",
     "iter_rambo24.hip",
     "iter_bw_flat.hip",
+    "vegas_serve.hip",
     "vegas_runtime.cpp",
     "vegas_server.cpp",
 ]

@@ -19,8 +19,9 @@ struct Layout {
 
 const char* status_name(int s);
 bool shape_ok(int dim, int nb);
-Layout layout(int dim, int nb);
-DevGrid bind_grid(void* ws, int dim, int nb);
+// max_partials workgroup/chunk partial slots, ring result entries.
+Layout layout(int dim, int nb, int max_partials = kMaxBlocks, int ring = kRing);
+DevGrid bind_grid(void* ws, int dim, int nb, int max_partials = kMaxBlocks, int ring = kRing);
 // Derived integrand constants; VEGAS_OK or VEGAS_EINVAL. out may be NULL.
 int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArgs* out);
 // Workgroups for the iteration kernel: enough to fill the GPU at its

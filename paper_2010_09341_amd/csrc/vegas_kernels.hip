@@ -3,8 +3,9 @@
 //   k_iterate   (vegas_iterate.hpp, instantiated in iter_*.hip) draw, map,
 //               integrand, moments, w^2 histogram
 //   k_finalize  fixed-order reduction of the workgroup partials into (I, sigma),
-//               and of the histogram copies into the iteration's histogram
-//   k_refine    smoothing, normalisation, compression, equal-share re-binning
+//               of the histogram copies into the iteration's histogram, and
+//               the refinement of every dimension (one wave per dimension)
+//   k_refine    refinement from a histogram set by the host
 //   k_init_grid / k_prepare / k_set_t   grid set-up and state writes
 //
 // The method: VegasFlow (arXiv:2010.09341) Sec. 1 (importance sampling on
@@ -17,16 +18,18 @@
 #include <type_traits>
 
 #include "vegas_device.hpp"
+#include "vegas_finalize.hpp"
 #include "vegas_iterate.hpp"
 #include "vegas_launch.hpp"
 
 namespace vegas {
 
 // ---------------------------------------------------------------------------
-// finalize: workgroup 0 reduces the partials in a fixed order and writes
-// (I, sigma, non-finite count, t) to results[t % ring], then advances t;
-// workgroup 1 + d reduces the histogram copies of dimension d (fixed copy
-// order) into hist and zeroes the copies for the next iteration.
+// finalize (+ refine): one wave per workgroup. Workgroup 0 reduces the
+// iteration's workgroup partials (fixed order) into (I, sigma) at
+// results[t % ring] and advances t; workgroup 1 + d reduces the histogram
+// copies of dimension d into hist (zeroing the copies) and, when asked,
+// refines dimension d from it.
 // ---------------------------------------------------------------------------
 struct FinArgs {
   uint32_t* t;
@@ -34,98 +37,34 @@ struct FinArgs {
   double* results;
   double* copies;
   double* hist;
+  double* edges;
+  Rec64* rec64;
+  Rec32* rec32;
   double n_events;
+  double alpha;
   int blocks;
   int ring;
   int dim;
   int nb;
+  int refine;
 };
 
-__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
-  const int cells = a.dim * a.nb;
+__global__ __launch_bounds__(64) void k_finalize(FinArgs a) {
+  extern __shared__ __align__(16) double fsm[];
   if (blockIdx.x == 0) {
-    double s1 = 0.0, s2 = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < a.blocks; i += blockDim.x) {
-      s1 += a.partials[4 * i];
-      s2 += a.partials[4 * i + 1];
-      b += a.partials[4 * i + 2];
-    }
-    __shared__ double red[3][4];
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    b = wave_sum(b);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-      red[0][wid] = s1;
-      red[1][wid] = s2;
-      red[2][wid] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double S1 = 0.0, S2 = 0.0, B = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        S1 += red[0][w];
-        S2 += red[1][w];
-        B += red[2][w];
-      }
-      const double N = a.n_events;
-      const double I = S1 / N;
-      const double var = (S2 / N - I * I) / (N - 1.0);
-      const uint32_t t = *a.t;
-      double* r = a.results + 4 * (size_t)(t % (uint32_t)a.ring);
-      r[0] = I;
-      r[1] = sqrt(var > 0.0 ? var : 0.0);
-      r[2] = B;
-      r[3] = (double)t;
-      *a.t = t + 1;
-    }
-  } else {
-    const int d = blockIdx.x - 1;
-    for (int k = threadIdx.x; k < a.nb; k += blockDim.x) {
-      const int idx = d * a.nb + k;
-      double v = 0.0;
-#pragma unroll
-      for (int c = 0; c < kHistCopies; ++c) {
-        v += a.copies[(size_t)c * cells + idx];
-        a.copies[(size_t)c * cells + idx] = 0.0;
-      }
-      a.hist[idx] = v;
-    }
+    wg_moments(a.partials, a.blocks, a.n_events, a.t, a.results, a.ring, nullptr);
+    return;
   }
+  const int d = blockIdx.x - 1;
+  const int nb = a.nb;
+  double* h = fsm;
+  wg_reduce_hist(a.copies, a.hist + (size_t)d * nb, a.dim * nb, d, nb, h);
+  if (a.refine)
+    wg_refine_dim(nb, a.alpha, a.edges + (size_t)d * (nb + 1), h, a.rec64 + (size_t)d * nb,
+                  a.rec32 + (size_t)d * nb, fsm + nb);
 }
 
-// ---------------------------------------------------------------------------
-// Grid records of one dimension from its edges in LDS (one wave).
-// ---------------------------------------------------------------------------
-__device__ void write_records(int d, int nb, const double* e, Rec64* rec64, Rec32* rec32) {
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-    const double lo = e[k], hi = e[k + 1];
-    rec64[d * nb + k] = Rec64{lo, hi - lo};
-    const float lo32 = (float)lo, hi32 = (float)hi;
-    const double w32 = (double)hi32 - (double)lo32;  // exact
-    const double jac = (double)nb * w32;
-    Rec32 r;
-    r.e = lo32;
-    r.w = (float)w32;
-    // a bin narrower than binary32 resolution carries a vanishing Jacobian
-    r.l2j = (float)log2(jac > 0x1p-1000 ? jac : 0x1p-1000);
-    r.pad = 0.f;
-    rec32[d * nb + k] = r;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// refine: one wave per dimension.
-//  1. smooth: s_i = (h_{i-1} + h_i + h_{i+1})/3, (h_0+h_1)/2 and
-//     (h_{nb-2}+h_{nb-1})/2 at the ends;
-//  2. p_i = s_i / sum s (a dimension with sum 0 keeps its edges);
-//  3. r_i = ((1 - p_i)/(-ln p_i))^alpha (0 for p_i = 0, 1 for p_i = 1);
-//  4. running sums C_k of r (per-lane contiguous segments, then a wave scan);
-//  5. new edge j at the point where the piecewise-uniform r density reaches
-//     j C_nb / nb: the old bin k is the smallest with C_{k+1} >= j C_nb/nb
-//     (binary search), the position linear inside it;
-//  6. e_0 = 0, e_nb = 1; records rebuilt.
-// ---------------------------------------------------------------------------
+// refine from the stored histogram (after the histogram was set by the host)
 struct RefArgs {
   double* edges;
   const double* hist;
@@ -139,91 +78,10 @@ __global__ __launch_bounds__(64) void k_refine(RefArgs a) {
   extern __shared__ __align__(16) double rsm[];
   const int nb = a.nb;
   const int d = blockIdx.x;
-  const int lane = threadIdx.x;
-  double* eo = rsm;            // nb + 1
-  double* en = eo + (nb + 1);  // nb + 1
-  double* C = en + (nb + 1);   // nb + 1
-  double* s = C + (nb + 1);    // nb
-  double* r = s + nb;          // nb
-  const double* h = a.hist + (size_t)d * nb;
-  double* erow = a.edges + (size_t)d * (nb + 1);
-  for (int i = lane; i <= nb; i += 64) eo[i] = erow[i];
-  for (int i = lane; i < nb; i += 64) r[i] = h[i];
+  for (int k = threadIdx.x; k < nb; k += 64) rsm[k] = a.hist[(size_t)d * nb + k];
   __syncthreads();
-  for (int i = lane; i < nb; i += 64) {
-    double v;
-    if (i == 0)
-      v = (r[0] + r[1]) / 2.0;
-    else if (i == nb - 1)
-      v = (r[nb - 2] + r[nb - 1]) / 2.0;
-    else
-      v = (r[i - 1] + r[i] + r[i + 1]) / 3.0;
-    s[i] = v;
-  }
-  __syncthreads();
-  double part = 0.0;
-  for (int i = lane; i < nb; i += 64) part += s[i];
-  const double S = wave_sum(part);
-  if (!(S > 0.0)) {
-    for (int i = lane; i <= nb; i += 64) en[i] = eo[i];
-  } else {
-    for (int i = lane; i < nb; i += 64) {
-      const double p = s[i] / S;
-      double v;
-      if (p <= 0.0)
-        v = 0.0;
-      else if (p >= 1.0)
-        v = 1.0;
-      else
-        v = pow((1.0 - p) / (-log(p)), a.alpha);
-      r[i] = v;
-    }
-    __syncthreads();
-    const int seg = (nb + 63) / 64;
-    const int lo = lane * seg;
-    const int hi = lo + seg < nb ? lo + seg : nb;
-    double local = 0.0;
-    for (int i = lo; i < hi; ++i) local += r[i];
-    double incl = local;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const double v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += v;
-    }
-    double excl = __shfl_up(incl, 1, 64);
-    if (lane == 0) excl = 0.0;
-    if (lo < nb) {
-      double c = excl;
-      C[lo] = c;
-      for (int i = lo; i < hi; ++i) {
-        c += r[i];
-        C[i + 1] = c;
-      }
-    }
-    if (lane == 0) C[0] = 0.0;
-    __syncthreads();
-    const double delta = C[nb] / nb;
-    for (int j = lane + 1; j < nb; j += 64) {
-      const double target = j * delta;
-      int lo_k = 0, hi_k = nb - 1;
-      while (lo_k < hi_k) {
-        const int mid = (lo_k + hi_k) >> 1;
-        if (C[mid + 1] >= target)
-          hi_k = mid;
-        else
-          lo_k = mid + 1;
-      }
-      const int k = lo_k;
-      en[j] = eo[k] + (target - C[k]) / r[k] * (eo[k + 1] - eo[k]);
-    }
-    if (lane == 0) {
-      en[0] = 0.0;
-      en[nb] = 1.0;
-    }
-  }
-  __syncthreads();
-  for (int i = lane; i <= nb; i += 64) erow[i] = en[i];
-  write_records(d, nb, en, a.rec64, a.rec32);
+  wg_refine_dim(nb, a.alpha, a.edges + (size_t)d * (nb + 1), rsm, a.rec64 + (size_t)d * nb,
+                a.rec32 + (size_t)d * nb, rsm + nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,21 +103,15 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
   const int nb = a.nb;
   const int d = blockIdx.x;
   double* erow = a.edges + (size_t)d * (nb + 1);
-  for (int i = threadIdx.x; i <= nb; i += 64) {
-    if (a.uniform) {
-      gsm[i] = (double)i / nb;
-      erow[i] = gsm[i];
-    } else {
-      gsm[i] = erow[i];
-    }
-  }
   if (a.uniform) {
-    for (int c = 0; c < kHistCopies; ++c)
-      for (int k = threadIdx.x; k < nb; k += 64) a.copies[(size_t)c * a.cells + d * nb + k] = 0.0;
+    wg_uniform_dim(nb, erow, a.copies, a.cells, d, a.rec64 + (size_t)d * nb,
+                   a.rec32 + (size_t)d * nb, gsm);
     if (d == 0 && threadIdx.x == 0) *a.t = 0;
+  } else {
+    for (int i = threadIdx.x; i <= nb; i += 64) gsm[i] = erow[i];
+    __syncthreads();
+    wg_write_records(nb, gsm, a.rec64 + (size_t)d * nb, a.rec32 + (size_t)d * nb);
   }
-  __syncthreads();
-  write_records(d, nb, gsm, a.rec64, a.rec32);
 }
 
 __global__ void k_set_t(uint32_t* t, uint32_t v) {
@@ -329,7 +181,8 @@ hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArg
                          iterate_lds_bytes(g.dim, g.nb), s);
 }
 
-hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, hipStream_t s) {
+hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, bool refine,
+                           double alpha, hipStream_t s) {
   if (blocks < 1 || blocks > g.max_blocks) return hipErrorInvalidValue;
   FinArgs a;
   a.t = g.t;
@@ -337,12 +190,18 @@ hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, hipSt
   a.results = g.results;
   a.copies = g.copies;
   a.hist = g.hist;
+  a.edges = g.edges;
+  a.rec64 = static_cast<Rec64*>(g.rec64);
+  a.rec32 = static_cast<Rec32*>(g.rec32);
   a.n_events = (double)n_events;
+  a.alpha = alpha;
   a.blocks = blocks;
   a.ring = g.ring;
   a.dim = g.dim;
   a.nb = g.nb;
-  hipLaunchKernelGGL(k_finalize, dim3(1 + g.dim), dim3(256), 0, s, a);
+  a.refine = refine ? 1 : 0;
+  const size_t lds = sizeof(double) * (g.nb + refine_lds_doubles(g.nb));
+  hipLaunchKernelGGL(k_finalize, dim3(1 + g.dim), dim3(64), lds, s, a);
   return hipGetLastError();
 }
 
@@ -354,7 +213,7 @@ hipError_t launch_refine(const DevGrid& g, double alpha, hipStream_t s) {
   a.rec32 = static_cast<Rec32*>(g.rec32);
   a.alpha = alpha;
   a.nb = g.nb;
-  const size_t lds = sizeof(double) * (3 * (size_t)(g.nb + 1) + 2 * (size_t)g.nb);
+  const size_t lds = sizeof(double) * (g.nb + refine_lds_doubles(g.nb));
   hipLaunchKernelGGL(k_refine, dim3(g.dim), dim3(64), lds, s, a);
   return hipGetLastError();
 }

@@ -48,9 +48,11 @@ hipError_t launch_iterate(const DevGrid& g, const IterLaunch& L, const Integrand
                           hipStream_t s);
 hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,
                        hipStream_t s);
-// Reduce block partials to (I, sigma) in results[t % ring], advance t, and
-// reduce the histogram copies into hist (zeroing the copies).
-hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, hipStream_t s);
+// Reduce block partials to (I, sigma) in results[t % ring], advance t,
+// reduce the histogram copies into hist (zeroing the copies) and, if refine,
+// refine the grid with exponent alpha.
+hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, bool refine,
+                           double alpha, hipStream_t s);
 hipError_t launch_refine(const DevGrid& g, double alpha, hipStream_t s);
 // Uniform grid, t = 0, zero histogram copies, grid records.
 hipError_t launch_init_grid(const DevGrid& g, hipStream_t s);

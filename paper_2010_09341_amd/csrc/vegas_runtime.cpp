@@ -39,7 +39,7 @@ bool shape_ok(int dim, int nb) {
          dim * nb <= VEGAS_MAX_CELLS;
 }
 
-Layout layout(int dim, int nb) {
+Layout layout(int dim, int nb, int max_partials, int ring) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   Layout L;
   size_t o = 0;
@@ -56,15 +56,15 @@ Layout layout(int dim, int nb) {
   L.rec32 = o;
   o = al(o + sizeof(Rec32) * dim * nb);
   L.partials = o;
-  o = al(o + sizeof(double) * 4 * kMaxBlocks);
+  o = al(o + sizeof(double) * 4 * (size_t)max_partials);
   L.results = o;
-  o = al(o + sizeof(double) * 4 * kRing);
+  o = al(o + sizeof(double) * 4 * (size_t)ring);
   L.total = o;
   return L;
 }
 
-DevGrid bind_grid(void* ws, int dim, int nb) {
-  const Layout L = layout(dim, nb);
+DevGrid bind_grid(void* ws, int dim, int nb, int max_partials, int ring) {
+  const Layout L = layout(dim, nb, max_partials, ring);
   char* b = static_cast<char*>(ws);
   DevGrid g;
   g.dim = dim;
@@ -77,8 +77,8 @@ DevGrid bind_grid(void* ws, int dim, int nb) {
   g.rec32 = b + L.rec32;
   g.partials = reinterpret_cast<double*>(b + L.partials);
   g.results = reinterpret_cast<double*>(b + L.results);
-  g.max_blocks = kMaxBlocks;
-  g.ring = kRing;
+  g.max_blocks = max_partials;
+  g.ring = ring;
   return g;
 }
 
@@ -321,9 +321,7 @@ hipError_t enqueue_iteration(vegas_h h, int fid, const IntegrandArgs& P, int64_t
   if ((e = launch_iterate(h->g, L, P, h->stream)) != hipSuccess) return e;
   if (h->timing && (e = hipEventRecord(h->events[2 * ev_slot + 1], h->stream)) != hipSuccess)
     return e;
-  if ((e = launch_finalize(h->g, blocks, n_events, h->stream)) != hipSuccess) return e;
-  if (refine && (e = launch_refine(h->g, alpha, h->stream)) != hipSuccess) return e;
-  return hipSuccess;
+  return launch_finalize(h->g, blocks, n_events, refine, alpha, h->stream);
 }
 
 hipError_t collect_timing(vegas_h h, size_t n) {

@@ -1,0 +1,440 @@
+// vegas_server.cpp — the serving loop behind vegas_server_* (include/vegas.h).
+//
+// A scheduler thread owns one HIP stream and one device arena (the memory
+// budget). Requests are admitted first-in first-out when a slot and arena
+// bytes are free; every admitted integral keeps its grid, histogram and
+// partial sums resident in its arena range. Each tick advances every
+// admitted integral by one iteration:
+//   1. newly admitted integrals get their uniform grid (k_serve_init);
+//   2. one launch per (precision, dimension class) runs every event chunk of
+//      every admitted integral's current iteration (k_serve_iterate), so
+//      small and large integrals share the GPU;
+//   3. one launch closes all those iterations: moments, histogram reduction
+//      and refinement (k_serve_finalize);
+//   4. the per-integral (I_t, sigma_t) come back in one 32-byte-per-integral
+//      copy; finished integrals free their slot and arena range, which the
+//      next tick can give to waiting requests.
+// Host-to-device inputs of a tick (new slot descriptors, work lists) travel
+// in one copy from pinned memory.
+#include <hip/hip_runtime_api.h>
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "vegas.h"
+#include "vegas_common.hpp"
+#include "vegas_sched.hpp"
+#include "vegas_serve.hpp"
+
+using namespace vegas;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+  uint64_t ticket = 0;
+  vegas_request r{};
+  std::vector<double> params;
+  IntegrandArgs P{};
+  int64_t chunk = 0;
+  uint32_t n_chunks = 0;
+  Layout L{};
+  int slot = -1;
+  size_t off = 0;
+  bool fresh = false;
+  int iters = 0;
+  std::vector<double> I_t, s_t;
+  int64_t bad = 0;
+  Clock::time_point t_submit, t_done;
+  bool done = false;
+  int status = VEGAS_OK;
+  double I = 0, sigma = 0, chi2 = 0;
+};
+
+Layout slot_layout(int dim, int nb, uint32_t n_chunks, int ring) {
+  return layout(dim, nb, (int)n_chunks, ring);
+}
+
+size_t slot_bytes(const Req* q) { return q->L.total; }
+
+template <class T>
+struct Pinned {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t reserve(size_t want) {
+    if (want <= n) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    size_t cap = want + want / 2 + 64;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p), cap * sizeof(T), hipHostMallocDefault);
+    if (e == hipSuccess) n = cap;
+    return e;
+  }
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t reserve(size_t want) {
+    if (want <= n) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    size_t cap = want + want / 2 + 64;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), cap * sizeof(T));
+    if (e == hipSuccess) n = cap;
+    return e;
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct vegas_srv {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* arena_dev = nullptr;
+  Arena arena;
+  int max_slots = 0;
+  int64_t chunk_fixed = 0;
+  SlotDev* slots_dev = nullptr;
+  SlotDev* slots_pin = nullptr;  // per-slot staging of descriptors
+  Pinned<unsigned char> in_pin;  // one tick's host-to-device inputs
+  DevBuf<unsigned char> in_dev;
+  Pinned<double> out_pin;
+  DevBuf<double> out_dev;
+
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  int error = VEGAS_OK;
+  std::unique_ptr<Admission<Req*>> adm;
+  std::map<uint64_t, std::unique_ptr<Req>> reqs;
+  uint64_t next_ticket = 1;
+  std::vector<Req*> active;  // by slot
+  int n_active = 0;
+  // statistics
+  int64_t completed = 0, events = 0, work_items = 0, peak_active = 0;
+
+  void run();
+  hipError_t tick(std::vector<Req*>& act);
+};
+
+hipError_t vegas_srv::tick(std::vector<Req*>& act) {
+  // ---- host-side tick lists ------------------------------------------------
+  std::vector<FinItem> init_items, fin_items;
+  std::vector<WorkItem> work[2][2];  // [prec][dim class 16 / 32]
+  int max_cells[2][2] = {{0, 0}, {0, 0}};
+  int max_nb = 2;
+  std::vector<Req*> fresh;
+  for (size_t i = 0; i < act.size(); ++i) {
+    Req* q = act[i];
+    const int dim = q->r.dim, nb = q->r.n_bins;
+    max_nb = std::max(max_nb, nb);
+    if (q->fresh) {
+      fresh.push_back(q);
+      for (int d = 0; d < dim; ++d) init_items.push_back(FinItem{(uint32_t)q->slot, d, 0, 0});
+    }
+    const int pc = q->r.prec == VEGAS_FP64 ? 0 : 1;
+    const int dc = dim <= 16 ? 0 : 1;
+    for (uint32_t c = 0; c < q->n_chunks; ++c) work[pc][dc].push_back(WorkItem{(uint32_t)q->slot, c});
+    max_cells[pc][dc] = std::max(max_cells[pc][dc], dim * nb);
+    const uint32_t refine = q->iters + 1 < q->r.n_iter ? 1u : 0u;
+    fin_items.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
+    for (int d = 0; d < dim; ++d) fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine});
+  }
+  // ---- pack the inputs into one pinned buffer ------------------------------
+  size_t bytes = (init_items.size() + fin_items.size()) * sizeof(FinItem);
+  for (auto& a : work)
+    for (auto& v : a) bytes += v.size() * sizeof(WorkItem);
+  hipError_t e;
+  if ((e = in_pin.reserve(bytes)) != hipSuccess) return e;
+  if ((e = in_dev.reserve(bytes)) != hipSuccess) return e;
+  if ((e = out_pin.reserve(4 * act.size())) != hipSuccess) return e;
+  if ((e = out_dev.reserve(4 * act.size())) != hipSuccess) return e;
+  size_t o = 0;
+  auto put = [&](const void* src, size_t n) {
+    const size_t at = o;
+    if (n) std::memcpy(in_pin.p + o, src, n);
+    o += n;
+    return at;
+  };
+  const size_t o_init = put(init_items.data(), init_items.size() * sizeof(FinItem));
+  const size_t o_fin = put(fin_items.data(), fin_items.size() * sizeof(FinItem));
+  size_t o_work[2][2];
+  for (int p = 0; p < 2; ++p)
+    for (int c = 0; c < 2; ++c) o_work[p][c] = put(work[p][c].data(), work[p][c].size() * sizeof(WorkItem));
+  // ---- device work ------------------------------------------------------------
+  for (Req* q : fresh) {
+    if ((e = hipMemcpyAsync(slots_dev + q->slot, slots_pin + q->slot, sizeof(SlotDev),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess)
+      return e;
+    q->fresh = false;
+  }
+  if (bytes && (e = hipMemcpyAsync(in_dev.p, in_pin.p, bytes, hipMemcpyHostToDevice, stream)) !=
+                   hipSuccess)
+    return e;
+  auto fin_at = [&](size_t off) { return reinterpret_cast<const FinItem*>(in_dev.p + off); };
+  auto work_at = [&](size_t off) { return reinterpret_cast<const WorkItem*>(in_dev.p + off); };
+  if ((e = launch_serve_init(slots_dev, fin_at(o_init), (int)init_items.size(), max_nb, stream)) !=
+      hipSuccess)
+    return e;
+  for (int p = 0; p < 2; ++p)
+    for (int c = 0; c < 2; ++c) {
+      if (work[p][c].empty()) continue;
+      if ((e = launch_serve_iterate(c == 0 ? 16 : 32, p == 0 ? VEGAS_FP64 : VEGAS_FP32_EVAL,
+                                    slots_dev, work_at(o_work[p][c]), (int)work[p][c].size(),
+                                    max_cells[p][c], stream)) != hipSuccess)
+        return e;
+    }
+  if ((e = launch_serve_finalize(slots_dev, fin_at(o_fin), (int)fin_items.size(), max_nb,
+                                 out_dev.p, stream)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(out_pin.p, out_dev.p, 4 * sizeof(double) * act.size(),
+                          hipMemcpyDeviceToHost, stream)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(stream);
+}
+
+void vegas_srv::run() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    if (error == VEGAS_OK) {
+      auto admitted = adm->admit(slot_bytes);
+      for (auto& a : admitted) {
+        Req* q = std::get<0>(a);
+        q->slot = std::get<1>(a);
+        q->off = std::get<2>(a);
+        q->fresh = true;
+        active[q->slot] = q;
+        ++n_active;
+        DevGrid g = bind_grid(static_cast<char*>(arena_dev) + q->off, q->r.dim, q->r.n_bins,
+                              (int)q->n_chunks, q->r.n_iter);
+        SlotDev S{};
+        S.t = g.t;
+        S.edges = g.edges;
+        S.hist = g.hist;
+        S.copies = g.copies;
+        S.rec64 = static_cast<Rec64*>(g.rec64);
+        S.rec32 = static_cast<Rec32*>(g.rec32);
+        S.partials = g.partials;
+        S.results = g.results;
+        S.n_events = (uint64_t)q->r.n_events;
+        S.chunk_events = (uint64_t)q->chunk;
+        S.n_chunks = q->n_chunks;
+        S.seed_lo = (uint32_t)q->r.seed;
+        S.seed_hi = (uint32_t)(q->r.seed >> 32);
+        S.dim = q->r.dim;
+        S.nb = (uint32_t)q->r.n_bins;
+        S.fid = q->r.integrand_id;
+        S.prec = q->r.prec;
+        S.ring = q->r.n_iter;
+        S.nb_pow_d = std::pow((double)q->r.n_bins, (double)q->r.dim);
+        S.alpha = q->r.alpha;
+        S.P = q->P;
+        slots_pin[q->slot] = S;
+      }
+      peak_active = std::max<int64_t>(peak_active, n_active);
+    }
+    if (n_active == 0 || error != VEGAS_OK) {
+      if (stop && (adm->pending() == 0 || error != VEGAS_OK)) break;
+      cv_work.wait(lk);
+      continue;
+    }
+    std::vector<Req*> act;
+    for (Req* q : active)
+      if (q) act.push_back(q);
+    lk.unlock();
+    const hipError_t e = tick(act);
+    lk.lock();
+    if (e != hipSuccess) {
+      error = VEGAS_EDEVICE;
+      for (Req* q : act) {
+        q->done = true;
+        q->status = VEGAS_EDEVICE;
+        q->t_done = Clock::now();
+      }
+      // requests still queued fail with the same status
+      for (auto& kv : reqs)
+        if (!kv.second->done) {
+          kv.second->done = true;
+          kv.second->status = VEGAS_EDEVICE;
+          kv.second->t_done = Clock::now();
+        }
+      cv_done.notify_all();
+      continue;
+    }
+    for (size_t i = 0; i < act.size(); ++i) {
+      Req* q = act[i];
+      work_items += q->n_chunks;
+      const double* r = out_pin.p + 4 * i;
+      q->I_t.push_back(r[0]);
+      q->s_t.push_back(r[1]);
+      q->bad += (int64_t)r[2];
+      q->iters += 1;
+      events += q->r.n_events;
+      if (q->iters == q->r.n_iter) {
+        q->t_done = Clock::now();
+        combine(q->I_t, q->s_t, &q->I, &q->sigma, &q->chi2);
+        q->status = q->bad > 0 ? VEGAS_ENONFINITE : VEGAS_OK;
+        q->done = true;
+        active[q->slot] = nullptr;
+        --n_active;
+        adm->finish(q->slot, q->off);
+        ++completed;
+      }
+    }
+    cv_done.notify_all();
+  }
+}
+
+extern "C" {
+
+int vegas_server_create(size_t mem_budget_bytes, int max_slots, int64_t chunk_events,
+                        vegas_server* out) {
+  if (!out || max_slots < 1 || max_slots > 4096 || chunk_events < 0 || mem_budget_bytes < 4096)
+    return VEGAS_EINVAL;
+  *out = nullptr;
+  auto s = std::make_unique<vegas_srv>();
+  s->max_slots = max_slots;
+  s->chunk_fixed = chunk_events;
+  if (hipGetDevice(&s->device) != hipSuccess) return VEGAS_EDEVICE;
+  hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(&s->arena_dev, mem_budget_bytes);
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&s->slots_dev), sizeof(SlotDev) * max_slots);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&s->slots_pin), sizeof(SlotDev) * max_slots,
+                      hipHostMallocDefault);
+  if (e != hipSuccess) {
+    const int rc = e == hipErrorOutOfMemory ? VEGAS_ENOMEM : VEGAS_EDEVICE;
+    if (s->slots_pin) (void)hipHostFree(s->slots_pin);
+    if (s->slots_dev) (void)hipFree(s->slots_dev);
+    if (s->arena_dev) (void)hipFree(s->arena_dev);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    return rc;
+  }
+  s->arena = Arena(mem_budget_bytes);
+  s->adm = std::make_unique<Admission<Req*>>(max_slots, &s->arena);
+  s->active.assign(max_slots, nullptr);
+  vegas_srv* raw = s.release();
+  raw->worker = std::thread([raw] { raw->run(); });
+  *out = raw;
+  return VEGAS_OK;
+}
+
+int vegas_server_submit(vegas_server s, const vegas_request* r, uint64_t* ticket) {
+  if (!s || !r || !ticket) return VEGAS_EINVAL;
+  if (!shape_ok(r->dim, r->n_bins) || r->n_events < 2 || r->n_iter < 1 ||
+      r->n_iter > VEGAS_MAX_RUN_ITER || !(r->alpha >= 0.0 && r->alpha <= VEGAS_MAX_ALPHA) ||
+      (r->prec != VEGAS_FP64 && r->prec != VEGAS_FP32_EVAL) || r->n_params < 0 ||
+      r->n_params > VEGAS_MAX_PARAMS || (r->n_params > 0 && !r->params))
+    return VEGAS_EINVAL;
+  auto q = std::make_unique<Req>();
+  q->r = *r;
+  q->params.assign(r->params, r->params + r->n_params);
+  q->r.params = nullptr;
+  if (build_integrand_args(r->integrand_id, r->dim, q->params.data(), r->n_params, &q->P) !=
+      VEGAS_OK)
+    return VEGAS_EINVAL;
+  q->chunk = chunk_events(r->n_events, s->chunk_fixed);
+  const int64_t nc = (r->n_events + q->chunk - 1) / q->chunk;
+  if (nc > (int64_t)UINT32_MAX / 2) return VEGAS_EINVAL;
+  q->n_chunks = (uint32_t)nc;
+  q->L = slot_layout(r->dim, r->n_bins, q->n_chunks, r->n_iter);
+  if (q->L.total > s->arena.size()) return VEGAS_ENOMEM;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->error != VEGAS_OK) return s->error;
+  if (s->stop) return VEGAS_ESTATE;
+  q->ticket = s->next_ticket++;
+  q->t_submit = Clock::now();
+  *ticket = q->ticket;
+  s->adm->push(q.get());
+  s->reqs[q->ticket] = std::move(q);
+  s->cv_work.notify_one();
+  return VEGAS_OK;
+}
+
+int vegas_server_wait(vegas_server s, uint64_t ticket, double timeout_s, double* I, double* sigma,
+                      double* chi2_dof, double* latency_s) {
+  if (!s) return VEGAS_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return VEGAS_EINVAL;
+  Req* q = it->second.get();
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, [&] { return q->done; });
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                                  [&] { return q->done; })) {
+    return VEGAS_EBUSY;
+  }
+  if (q->status == VEGAS_EDEVICE) return VEGAS_EDEVICE;
+  if (I) *I = q->I;
+  if (sigma) *sigma = q->sigma;
+  if (chi2_dof) *chi2_dof = q->chi2;
+  if (latency_s) *latency_s = std::chrono::duration<double>(q->t_done - q->t_submit).count();
+  return q->status;
+}
+
+int vegas_server_iterations(vegas_server s, uint64_t ticket, double* I_t, double* sigma_t) {
+  if (!s) return VEGAS_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return VEGAS_EINVAL;
+  Req* q = it->second.get();
+  if (!q->done) return VEGAS_EBUSY;
+  if (q->status == VEGAS_EDEVICE) return VEGAS_EDEVICE;
+  for (size_t i = 0; i < q->I_t.size(); ++i) {
+    if (I_t) I_t[i] = q->I_t[i];
+    if (sigma_t) sigma_t[i] = q->s_t[i];
+  }
+  return VEGAS_OK;
+}
+
+int vegas_server_stats(vegas_server s, int64_t* completed, int64_t* events, int64_t* work_items,
+                       int64_t* peak_active) {
+  if (!s) return VEGAS_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (completed) *completed = s->completed;
+  if (events) *events = s->events;
+  if (work_items) *work_items = s->work_items;
+  if (peak_active) *peak_active = s->peak_active;
+  return VEGAS_OK;
+}
+
+int vegas_server_destroy(vegas_server s) {
+  if (!s) return VEGAS_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  const int rc = s->error;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->slots_pin) (void)hipHostFree(s->slots_pin);
+  if (s->slots_dev) (void)hipFree(s->slots_dev);
+  if (s->arena_dev) (void)hipFree(s->arena_dev);
+  (void)hipStreamDestroy(s->stream);
+  delete s;
+  return rc;
+}
+
+}  // extern "C"

@@ -277,3 +277,78 @@ def vegas_timing(h: Handle, enable: bool, reset: bool = False):
     _check(lib().vegas_timing(h, int(enable), int(reset), _c.byref(ms), _c.byref(n)),
            "vegas_timing")
     return ms.value, n.value
+
+
+# ---- serving -----------------------------------------------------------------
+class vegas_request(ctypes.Structure):
+    _fields_ = [("dim", _c.c_int), ("n_bins", _c.c_int), ("integrand_id", _c.c_int),
+                ("n_params", _c.c_int), ("params", _pd), ("n_events", _i64),
+                ("n_iter", _c.c_int), ("alpha", _c.c_double), ("seed", _u64),
+                ("prec", _c.c_int)]
+
+
+class Server:
+    """An opaque vegas_server."""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    @property
+    def _as_parameter_(self):
+        return self.ptr
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                vegas_server_destroy(self)
+        except Exception:
+            pass
+
+
+def vegas_server_create(mem_budget_bytes: int, max_slots: int, chunk_events: int = 0) -> Server:
+    out = _vp()
+    _check(lib().vegas_server_create(mem_budget_bytes, max_slots, chunk_events, _c.byref(out)),
+           "vegas_server_create")
+    return Server(out.value)
+
+
+def vegas_server_submit(s: Server, dim: int, n_bins: int, integrand_id: int, params,
+                        n_events: int, n_iter: int, alpha: float, seed: int,
+                        prec: int = VEGAS_FP32_EVAL) -> int:
+    p = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
+    req = vegas_request(dim, n_bins, integrand_id, int(p.size), _dptr(p) if p.size else None,
+                        n_events, n_iter, alpha, seed, prec)
+    t = _u64()
+    _check(lib().vegas_server_submit(s, _c.byref(req), _c.byref(t)), "vegas_server_submit")
+    return t.value
+
+
+def vegas_server_wait(s: Server, ticket: int, timeout_s: float = -1.0):
+    """(I, sigma, chi2_dof, latency_s) of a finished request."""
+    I, sg, c2, lat = _c.c_double(), _c.c_double(), _c.c_double(), _c.c_double()
+    _check(lib().vegas_server_wait(s, ticket, timeout_s, _c.byref(I), _c.byref(sg), _c.byref(c2),
+                                   _c.byref(lat)), "vegas_server_wait",
+           ok=(VEGAS_OK, VEGAS_ENONFINITE))
+    return I.value, sg.value, c2.value, lat.value
+
+
+def vegas_server_iterations(s: Server, ticket: int, n_iter: int):
+    I_t = np.zeros(n_iter)
+    s_t = np.zeros(n_iter)
+    _check(lib().vegas_server_iterations(s, ticket, _dptr(I_t), _dptr(s_t)),
+           "vegas_server_iterations")
+    return I_t, s_t
+
+
+def vegas_server_stats(s: Server):
+    """(completed, events, work_items, peak_active)."""
+    v = [_i64() for _ in range(4)]
+    _check(lib().vegas_server_stats(s, *[_c.byref(x) for x in v]), "vegas_server_stats")
+    return tuple(x.value for x in v)
+
+
+def vegas_server_destroy(s: Server):
+    if s.ptr:
+        rc = lib().vegas_server_destroy(s.ptr)
+        s.ptr = None
+        _check(rc, "vegas_server_destroy")

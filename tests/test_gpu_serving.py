@@ -1,0 +1,148 @@
+"""Serving loop on the GPU: many integrals of different shapes advance
+together, each with the result it has alone (within 1e-12), matching the
+oracle in FP64 mode; admission by slots and by a device-memory budget."""
+import numpy as np
+import pytest
+
+from paper_2010_09341_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    from paper_2010_09341_amd import vegas
+    vegas.lib()
+    return vegas
+
+
+def _submit(vg, srv, r: W.Request, prec=None):
+    return vg.vegas_server_submit(srv, r.dim, r.nb, r.fid, r.params, r.n_events, r.n_iter,
+                                  r.alpha, r.seed, r.prec if prec is None else prec)
+
+
+def test_served_fp64_matches_oracle(vg, orc):
+    srv = vg.vegas_server_create(1 << 28, 64)
+    reqs = [W.Request(0, 0.0, 4, 50, W.F_GAUSS, [0.1], 100_000, 5, 1.5, 0, W.FP64),
+            W.Request(1, 0.0, 3, 37, W.F_BW_FLAT, [0.42, 0.03], 20_011, 6, 1.5, 7, W.FP64),
+            W.Request(2, 0.0, 20, 8, W.F_SUM, None, 9_999, 3, 1.5, 3, W.FP64),
+            W.Request(3, 0.0, 4, 100, W.F_LO_TOY, [13000.0, 91.19, 2.5, 20.0], 50_000, 3,
+                      1.5, 1, W.FP64)]
+    tickets = [_submit(vg, srv, r) for r in reqs]
+    for r, tk in zip(reqs, tickets):
+        I, s, c2, lat = vg.vegas_server_wait(srv, tk, 120.0)
+        I_t, s_t = vg.vegas_server_iterations(srv, tk, r.n_iter)
+        I_r, s_r, _, _ = orc.run(r.dim, r.nb, r.fid, r.params, r.n_events, r.seed, r.n_iter,
+                                 r.alpha)
+        assert np.all(np.abs(I_t - I_r) <= 1e-12 * np.abs(I_r)), (r.index, I_t, I_r)
+        assert np.all(np.abs(s_t - s_r) <= 1e-10 * np.abs(s_r))
+        I_o, s_o, _ = orc.combine(I_r, s_r)
+        assert abs(I - I_o) <= 1e-12 * abs(I_o)
+        assert lat > 0
+    done, events, items, peak = vg.vegas_server_stats(srv)
+    assert done == 4 and events == sum(r.n_events * r.n_iter for r in reqs)
+    vg.vegas_server_destroy(srv)
+
+
+def test_alone_equals_in_the_mix(vg):
+    """20 requests from the serving trace, each run alone on its own server,
+    then all 200 trace requests together: the 20 agree within 1e-12."""
+    trace = W.serving_trace(200, rate_per_s=1e9, seed=3, max_events=300_000)
+    picks = trace[::10]
+    alone = {}
+    for r in picks:
+        srv = vg.vegas_server_create(1 << 28, 4)
+        tk = _submit(vg, srv, r)
+        vg.vegas_server_wait(srv, tk, 120.0)
+        alone[r.index] = vg.vegas_server_iterations(srv, tk, r.n_iter)
+        vg.vegas_server_destroy(srv)
+    srv = vg.vegas_server_create(1 << 30, 256)
+    tickets = {r.index: _submit(vg, srv, r) for r in trace}
+    for r in trace:
+        vg.vegas_server_wait(srv, tickets[r.index], 300.0)
+    for r in picks:
+        I_t, s_t = vg.vegas_server_iterations(srv, tickets[r.index], r.n_iter)
+        I_a, s_a = alone[r.index]
+        assert np.all(np.abs(I_t - I_a) <= 1e-12 * np.abs(I_a)), (r.index, I_t - I_a)
+        assert np.all(np.abs(s_t - s_a) <= 1e-10 * np.abs(s_a))
+    done, events, items, peak = vg.vegas_server_stats(srv)
+    assert done == len(trace)
+    assert peak > 1  # requests overlapped on the device
+    vg.vegas_server_destroy(srv)
+
+
+def test_served_closed_forms(vg):
+    trace = W.serving_trace(40, rate_per_s=1e9, seed=5, max_events=1_000_000)
+    srv = vg.vegas_server_create(1 << 28, 16)
+    tickets = [_submit(vg, srv, r) for r in trace]
+    pulls = []
+    for r, tk in zip(trace, tickets):
+        I, s, c2, _ = vg.vegas_server_wait(srv, tk, 120.0)
+        # first iterations on the uniform grid are the least precise; the
+        # combined estimate must still sit on the closed form
+        pulls.append((I - W.request_closed_form(r)) / s)
+    pulls = np.array(pulls)
+    assert np.mean(np.abs(pulls) < 4) > 0.9
+    vg.vegas_server_destroy(srv)
+
+
+def test_admission_by_memory_and_slots(vg):
+    """A budget that holds at most two of these integrals at a time, and a
+    request larger than the whole budget."""
+    from paper_2010_09341_amd.vegas import vegas_workspace_bytes
+    # a handle's workspace (4096 partial slots, 1024 result entries) is a bit
+    # more than twice a served 12 x 100 integral with 5 chunks and 4 iterations
+    budget = vegas_workspace_bytes(12, 100)
+    srv = vg.vegas_server_create(budget, 64)
+    reqs = [W.Request(i, 0.0, 12, 100, W.F_GAUSS, [0.2], 20_000, 4, 1.5, i, W.FP32_EVAL)
+            for i in range(8)]
+    tks = [_submit(vg, srv, r) for r in reqs]
+    for tk in tks:
+        vg.vegas_server_wait(srv, tk, 120.0)
+    done, _, _, peak = vg.vegas_server_stats(srv)
+    assert done == 8 and 1 <= peak <= 2
+    with pytest.raises(vg.VegasError) as e:
+        # 38147 chunk partial slots alone exceed the budget
+        vg.vegas_server_submit(srv, 12, 100, W.F_GAUSS, [0.2], 10**10, 4, 1.5, 0)
+    assert e.value.code == vg.VEGAS_ENOMEM
+    vg.vegas_server_destroy(srv)
+    srv = vg.vegas_server_create(1 << 28, 2)
+    tks = [_submit(vg, srv, r) for r in reqs]
+    for tk in tks:
+        vg.vegas_server_wait(srv, tk, 120.0)
+    assert vg.vegas_server_stats(srv)[3] == 2
+    vg.vegas_server_destroy(srv)
+
+
+def test_served_matches_handle(vg):
+    """The serving path and the single-integral path compute the same
+    iterations (different launch shapes: agreement to rounding)."""
+    r = W.Request(0, 0.0, 8, 50, W.F_GAUSS, [0.1], 1_000_000, 4, 1.5, 11, W.FP32_EVAL)
+    srv = vg.vegas_server_create(1 << 28, 8)
+    tk = _submit(vg, srv, r)
+    vg.vegas_server_wait(srv, tk, 120.0)
+    I_s, s_s = vg.vegas_server_iterations(srv, tk, r.n_iter)
+    vg.vegas_server_destroy(srv)
+    h = vg.vegas_create(8, 50)
+    vg.vegas_set_params(h, W.F_GAUSS, [0.1])
+    vg.vegas_set_precision(h, W.FP32_EVAL)
+    I_h, s_h = vg.vegas_run(h, W.F_GAUSS, r.n_events, r.seed, r.n_iter, r.alpha)
+    assert np.all(np.abs(I_s - I_h) <= 1e-12 * np.abs(I_h))
+
+
+def test_submit_validation(vg):
+    srv = vg.vegas_server_create(1 << 24, 4)
+    bad = [dict(dim=0), dict(n_bins=1), dict(n_events=1), dict(n_iter=0), dict(alpha=-1.0),
+           dict(integrand_id=99), dict(prec=7), dict(integrand_id=W.F_LO_TOY)]
+    base = dict(dim=3, n_bins=10, integrand_id=W.F_GAUSS, params=[0.2], n_events=1000,
+                n_iter=2, alpha=1.5, seed=0, prec=W.FP64)
+    for b in bad:
+        kw = dict(base)
+        kw.update(b)
+        with pytest.raises(vg.VegasError) as e:
+            vg.vegas_server_submit(srv, **kw)
+        assert e.value.code == vg.VEGAS_EINVAL, b
+    vg.vegas_server_destroy(srv)
