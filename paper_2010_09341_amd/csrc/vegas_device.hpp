@@ -259,25 +259,6 @@ __device__ __forceinline__ F32Val integrand_f32(const float* x, int DMAX, int D,
   return r;
 }
 
-// ---------------------------------------------------------------------------
-// LDS cell of (dimension d, bin k): the grid record and the bin's w^2 sum,
-// 32 bytes at byte offset (d * nb + k) * 32 of the workgroup's LDS, so the
-// record is one 16-byte-aligned LDS read and the sum one LDS atomic.
-// ---------------------------------------------------------------------------
-struct alignas(16) Cell64 {
-  double e, w;  // e_k, e_{k+1} - e_k
-  double h;     // sum of w^2
-  double pad;
-};
-struct alignas(16) Cell32 {
-  float e, w, l2j, pad;  // binary32 record (see Rec32)
-  double h;
-  double pad2;
-};
-static_assert(sizeof(Cell64) == 32 && sizeof(Cell32) == 32, "32-byte LDS cells");
-constexpr int kCellBytes = 32;
-constexpr int kCellHistOffset = 16;
-
 // Dimension count: D_T > 0 is the exact count known at compile time; D_T < 0
 // means at most -D_T dimensions with the actual count D given at run time.
 template <int D_T>
@@ -287,18 +268,65 @@ struct Dims {
   __device__ static constexpr bool on(int d, int D) { return D_T > 0 ? d < D_T : d < D; }
 };
 
+// Stage the grid records of the integral into LDS and zero the histograms.
+template <int PREC>
+__device__ inline void stage_grid(const void* rec, const LdsLayout& L, unsigned char* smem) {
+  const int cells = (int)L.cells;
+  if constexpr (PREC == kFp64) {
+    const Rec64* g = static_cast<const Rec64*>(rec);
+    double* e = reinterpret_cast<double*>(smem);
+    double* w = e + cells;
+    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+      const Rec64 r = g[i];
+      e[i] = r.e;
+      w[i] = r.w;
+    }
+  } else {
+    const Rec32* g = static_cast<const Rec32*>(rec);
+    float2* ew = reinterpret_cast<float2*>(smem);
+    float2* lj = ew + cells;
+    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+      const Rec32 r = g[i];
+      ew[i] = make_float2(r.e, r.w);
+      lj[i] = make_float2(r.l2j, 0.f);
+    }
+  }
+  double* h = reinterpret_cast<double*>(smem + L.hist_off);
+  const int nh = (int)(L.cstride * L.copies);
+  for (int i = threadIdx.x; i < nh; i += blockDim.x) h[i] = 0.0;
+}
+
+// Byte address, in LDS, of this lane's histogram copy.
+__device__ inline uint32_t lane_hist_base(const LdsLayout& L) {
+  return L.hist_off + 8u * L.cstride * (threadIdx.x & (L.copies - 1u));
+}
+
+// Add the LDS histogram copies of cell i and flush non-zero sums into dst
+// (global binary64 atomics). Needs a barrier before it.
+__device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem, double* dst) {
+  const double* h = reinterpret_cast<const double*>(smem + L.hist_off);
+  for (int i = threadIdx.x; i < (int)L.cells; i += blockDim.x) {
+    double v = h[i];
+    for (uint32_t c = 1; c < L.copies; ++c) v += h[c * L.cstride + i];
+    if (v != 0.0) __hip_atomic_fetch_add(&dst[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One event: draw, map, evaluate. Returns w = f(x) * J in binary64 and, in
-// cell[d], the LDS byte offset of the cell that dimension d fell into.
+// hist[d], the LDS byte address of the histogram entry that dimension d fell
+// into (in this lane's copy).
 // ---------------------------------------------------------------------------
 template <int D_T, int FID, int PREC>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
                                                int D, uint32_t nb, double nb_pow_d,
-                                               const unsigned char* lds, const IntegrandArgs& P,
-                                               uint32_t* cell) {
+                                               const unsigned char* lds, const LdsLayout& L,
+                                               uint32_t hbase, const IntegrandArgs& P,
+                                               uint32_t* hist) {
   using Dm = Dims<D_T>;
   const uint32_t n_lo = (uint32_t)n, n_hi = (uint32_t)(n >> 32);
-  const uint32_t row = nb * (uint32_t)kCellBytes;
+  const uint32_t row = nb * 8u;
+  const uint32_t second = 8u * L.cells;
   if constexpr (PREC == kFp64) {
     double x[Dm::kMax];
     double jac = 1.0;
@@ -315,12 +343,13 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const uint32_t rem = (uint32_t)prod;
             // (rem + 1/2) 2^-32, exact in binary64
             const double frac = fma((double)rem, 0x1p-32, 0x1p-33);
-            const uint32_t off = (k << 5) + (uint32_t)d * row;
-            const Cell64* c =
-                static_cast<const Cell64*>(__builtin_assume_aligned(lds + off, 16));
-            x[d] = fma(frac, c->w, c->e);
-            jac *= c->w;
-            cell[d] = off;
+            const uint32_t a = (uint32_t)d * row + (k << 3);
+            const double e = *static_cast<const double*>(__builtin_assume_aligned(lds + a, 8));
+            const double w =
+                *static_cast<const double*>(__builtin_assume_aligned(lds + a + second, 8));
+            x[d] = fma(frac, w, e);
+            jac *= w;
+            hist[d] = hbase + a;
           }
         }
       }
@@ -346,12 +375,13 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             // of a 2^-23 cell, exact in binary32
             const float frac =
                 __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u)) - 0x1.fffffep-1f;
-            const uint32_t off = (k << 5) + (uint32_t)d * row;
-            const Cell32* c =
-                static_cast<const Cell32*>(__builtin_assume_aligned(lds + off, 16));
-            x[d] = fmaf(frac, c->w, c->e);
-            l2j += c->l2j;
-            cell[d] = off;
+            const uint32_t a = (uint32_t)d * row + (k << 3);
+            const float2 ew = *static_cast<const float2*>(__builtin_assume_aligned(lds + a, 8));
+            const float lj =
+                *static_cast<const float*>(__builtin_assume_aligned(lds + a + second, 8));
+            x[d] = fmaf(frac, ew.y, ew.x);
+            l2j += lj;
+            hist[d] = hbase + a;
           }
         }
       }

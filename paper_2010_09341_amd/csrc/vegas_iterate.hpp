@@ -23,6 +23,7 @@ struct IterArgsDev {
   uint64_t n_events;  // events of the iteration (dump: number of events to dump)
   uint64_t first;     // dump: index of the first event
   double nb_pow_d;    // nb^D, the constant factor of the Jacobian
+  LdsLayout lds;
   uint32_t seed_lo, seed_hi;
   int dim;
   uint32_t nb;
@@ -34,48 +35,27 @@ template <int D_T, int FID, int PREC, bool DUMP>
 __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, IntegrandArgs P) {
   extern __shared__ __align__(16) unsigned char smem[];
   using Dm = Dims<D_T>;
-  const int cells = a.dim * (int)a.nb;
-  if constexpr (PREC == kFp64) {
-    const Rec64* g = static_cast<const Rec64*>(a.rec);
-    Cell64* c = reinterpret_cast<Cell64*>(smem);
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-      const Rec64 r = g[i];
-      c[i].e = r.e;
-      c[i].w = r.w;
-      c[i].h = 0.0;
-      c[i].pad = 0.0;
-    }
-  } else {
-    const Rec32* g = static_cast<const Rec32*>(a.rec);
-    Cell32* c = reinterpret_cast<Cell32*>(smem);
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-      const Rec32 r = g[i];
-      c[i].e = r.e;
-      c[i].w = r.w;
-      c[i].l2j = r.l2j;
-      c[i].pad = 0.f;
-      c[i].h = 0.0;
-      c[i].pad2 = 0.0;
-    }
-  }
+  const LdsLayout L = a.lds;
+  stage_grid<PREC>(a.rec, L, smem);
   __syncthreads();
 
   const uint32_t t = *a.t;
+  const uint32_t hbase = lane_hist_base(L);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t cell[Dm::kMax];
+  uint32_t hist[Dm::kMax];
 
   if constexpr (DUMP) {
     for (; n < a.n_events; n += stride)
       a.w_out[n] = event_weight<D_T, FID, PREC>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
-                                                a.nb, a.nb_pow_d, smem, P, cell);
+                                                a.nb, a.nb_pow_d, smem, L, hbase, P, hist);
     return;
   } else {
     double s1 = 0.0, s2 = 0.0;
     uint32_t bad = 0;
     for (; n < a.n_events; n += stride) {
       double w = event_weight<D_T, FID, PREC>(n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
-                                              a.nb_pow_d, smem, P, cell);
+                                              a.nb_pow_d, smem, L, hbase, P, hist);
       if (!__builtin_isfinite(w)) {
         ++bad;
         w = 0.0;
@@ -86,9 +66,8 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
 #pragma unroll
       for (int d = 0; d < Dm::kMax; ++d)
         if (Dm::on(d, a.dim))
-          __hip_atomic_fetch_add(
-              static_cast<double*>(__builtin_assume_aligned(smem + cell[d] + kCellHistOffset, 16)), w2,
-              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_fetch_add(static_cast<double*>(__builtin_assume_aligned(smem + hist[d], 8)),
+                                 w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
     __shared__ double red[3][kIterThreadsMax / 64];
@@ -115,12 +94,7 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
       p[2] = ab;
       p[3] = 0.0;
     }
-    double* dst = a.copies + (size_t)(blockIdx.x % kHistCopies) * cells;
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-      const double v = *reinterpret_cast<const double*>(smem + i * kCellBytes + kCellHistOffset);
-      if (v != 0.0)
-        __hip_atomic_fetch_add(&dst[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    flush_hist(L, smem, a.copies + (size_t)(blockIdx.x % kHistCopies) * L.cells);
   }
 }
 

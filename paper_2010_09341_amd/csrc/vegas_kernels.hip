@@ -134,7 +134,7 @@ const void* iterate_kernel(int fid, int prec, int dim, bool dump) {
   }
 }
 
-size_t iterate_lds_bytes(int dim, int nb) { return (size_t)dim * nb * kCellBytes; }
+size_t iterate_lds_bytes(int dim, int nb) { return lds_bytes(lds_layout(dim, nb)); }
 
 static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   IterArgsDev a;
@@ -150,6 +150,7 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.dim = g.dim;
   a.nb = (uint32_t)g.nb;
   a.nb_pow_d = pow((double)g.nb, (double)g.dim);
+  a.lds = lds_layout(g.dim, g.nb);
   return a;
 }
 

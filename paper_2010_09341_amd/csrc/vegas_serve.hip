@@ -23,39 +23,20 @@ namespace vegas {
 template <int D_T, int FID, int PREC>
 __device__ void serve_chunk(const SlotDev& S, uint32_t chunk, unsigned char* smem) {
   using Dm = Dims<D_T>;
-  const int cells = S.dim * (int)S.nb;
-  if constexpr (PREC == kFp64) {
-    Cell64* c = reinterpret_cast<Cell64*>(smem);
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-      const Rec64 r = S.rec64[i];
-      c[i].e = r.e;
-      c[i].w = r.w;
-      c[i].h = 0.0;
-      c[i].pad = 0.0;
-    }
-  } else {
-    Cell32* c = reinterpret_cast<Cell32*>(smem);
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-      const Rec32 r = S.rec32[i];
-      c[i].e = r.e;
-      c[i].w = r.w;
-      c[i].l2j = r.l2j;
-      c[i].pad = 0.f;
-      c[i].h = 0.0;
-      c[i].pad2 = 0.0;
-    }
-  }
+  const LdsLayout L = lds_layout(S.dim, (int)S.nb);
+  stage_grid<PREC>(PREC == kFp64 ? (const void*)S.rec64 : (const void*)S.rec32, L, smem);
   __syncthreads();
   const uint32_t t = *S.t;
+  const uint32_t hbase = lane_hist_base(L);
   const uint64_t begin = (uint64_t)chunk * S.chunk_events;
   uint64_t end = begin + S.chunk_events;
   if (end > S.n_events) end = S.n_events;
   double s1 = 0.0, s2 = 0.0;
   uint32_t bad = 0;
-  uint32_t cell[Dm::kMax];
+  uint32_t hist[Dm::kMax];
   for (uint64_t n = begin + threadIdx.x; n < end; n += blockDim.x) {
     double w = event_weight<D_T, FID, PREC>(n, t, S.seed_lo, S.seed_hi, S.dim, S.nb, S.nb_pow_d,
-                                            smem, S.P, cell);
+                                            smem, L, hbase, S.P, hist);
     if (!__builtin_isfinite(w)) {
       ++bad;
       w = 0.0;
@@ -66,9 +47,8 @@ __device__ void serve_chunk(const SlotDev& S, uint32_t chunk, unsigned char* sme
 #pragma unroll
     for (int d = 0; d < Dm::kMax; ++d)
       if (Dm::on(d, S.dim))
-        __hip_atomic_fetch_add(
-            static_cast<double*>(__builtin_assume_aligned(smem + cell[d] + kCellHistOffset, 16)),
-            w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(static_cast<double*>(__builtin_assume_aligned(smem + hist[d], 8)),
+                               w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __shared__ double red[3][kServeThreads / 64];
   s1 = wave_sum(s1);
@@ -94,11 +74,7 @@ __device__ void serve_chunk(const SlotDev& S, uint32_t chunk, unsigned char* sme
     p[2] = ab;
     p[3] = 0.0;
   }
-  double* dst = S.copies + (size_t)(chunk % kHistCopies) * cells;
-  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-    const double v = *reinterpret_cast<const double*>(smem + i * kCellBytes + kCellHistOffset);
-    if (v != 0.0) __hip_atomic_fetch_add(&dst[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  flush_hist(L, smem, S.copies + (size_t)(chunk % kHistCopies) * L.cells);
   __syncthreads();  // the LDS is reused by the next work item
 }
 
@@ -156,9 +132,9 @@ __global__ __launch_bounds__(64) void k_serve_init(const SlotDev* slots, const F
 }
 
 hipError_t launch_serve_iterate(int dmax, int prec, const SlotDev* slots, const WorkItem* items,
-                                int n_items, int max_cells, hipStream_t s) {
+                                int n_items, int max_lds, hipStream_t s) {
   if (n_items < 1) return hipSuccess;
-  const size_t lds = (size_t)max_cells * kCellBytes;
+  const size_t lds = (size_t)max_lds;
   const int blocks = n_items < kServeMaxBlocks ? n_items : kServeMaxBlocks;
   void* args[] = {&slots, &items, &n_items};
   const void* k = nullptr;

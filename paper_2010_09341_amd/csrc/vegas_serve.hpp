@@ -54,7 +54,7 @@ struct FinItem {
 };
 
 hipError_t launch_serve_iterate(int dmax, int prec, const SlotDev* slots, const WorkItem* items,
-                                int n_items, int max_cells, hipStream_t s);
+                                int n_items, int max_lds, hipStream_t s);
 hipError_t launch_serve_finalize(const SlotDev* slots, const FinItem* items, int n_items,
                                  int max_nb, double* out, hipStream_t s);
 hipError_t launch_serve_init(const SlotDev* slots, const FinItem* items, int n_items, int max_nb,

@@ -140,7 +140,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   // ---- host-side tick lists ------------------------------------------------
   std::vector<FinItem> init_items, fin_items;
   std::vector<WorkItem> work[2][2];  // [prec][dim class 16 / 32]
-  int max_cells[2][2] = {{0, 0}, {0, 0}};
+  int max_lds[2][2] = {{0, 0}, {0, 0}};
   int max_nb = 2;
   std::vector<Req*> fresh;
   for (size_t i = 0; i < act.size(); ++i) {
@@ -154,7 +154,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
     const int pc = q->r.prec == VEGAS_FP64 ? 0 : 1;
     const int dc = dim <= 16 ? 0 : 1;
     for (uint32_t c = 0; c < q->n_chunks; ++c) work[pc][dc].push_back(WorkItem{(uint32_t)q->slot, c});
-    max_cells[pc][dc] = std::max(max_cells[pc][dc], dim * nb);
+    max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(lds_layout(dim, nb)));
     const uint32_t refine = q->iters + 1 < q->r.n_iter ? 1u : 0u;
     fin_items.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
     for (int d = 0; d < dim; ++d) fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine});
@@ -200,7 +200,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
       if (work[p][c].empty()) continue;
       if ((e = launch_serve_iterate(c == 0 ? 16 : 32, p == 0 ? VEGAS_FP64 : VEGAS_FP32_EVAL,
                                     slots_dev, work_at(o_work[p][c]), (int)work[p][c].size(),
-                                    max_cells[p][c], stream)) != hipSuccess)
+                                    max_lds[p][c], stream)) != hipSuccess)
         return e;
     }
   if ((e = launch_serve_finalize(slots_dev, fin_at(o_fin), (int)fin_items.size(), max_nb,

@@ -2,6 +2,7 @@
 // runtime of the Vegas library (no device code).
 #pragma once
 
+#include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
 namespace vegas {
@@ -37,6 +38,37 @@ struct Rec64 {
 struct alignas(16) Rec32 {
   float e, w, l2j, pad;
 };
+
+// LDS layout of the iteration kernels' workgroups (cells = dim * nb, cell
+// (d, k) = d * nb + k):
+//   [0, 8 cells)        FP64: e_k            FP32: {e_k, w_k} (binary32 pair)
+//   [8 cells, 16 cells) FP64: w_k            FP32: log2(nb w_k) in the low word
+//   [hist_off, ...)     `copies` histograms of w^2 (binary64), copy stride
+//                       cstride entries; lane l adds into copy l % copies
+// Every random access is 8 bytes at an 8-byte stride (4 bytes for the
+// binary32 log2), which keeps LDS bank conflicts low; the histogram copies
+// split the lanes of a wave that hit the same bin. At most 64 KiB.
+struct LdsLayout {
+  uint32_t cells;
+  uint32_t hist_off;  // bytes
+  uint32_t cstride;   // histogram copy stride in entries
+  uint32_t copies;    // 1, 2 or 4
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int dim, int nb) {
+  LdsLayout L;
+  L.cells = (uint32_t)(dim * nb);
+  L.hist_off = 16u * L.cells;
+  L.cstride = L.cells + 4u;
+  const uint32_t budget = 65536u;
+  L.copies = 4u;
+  while (L.copies > 1u && L.hist_off + 8u * L.cstride * L.copies > budget) L.copies >>= 1;
+  return L;
+}
+
+__host__ __device__ inline uint32_t lds_bytes(const LdsLayout& L) {
+  return L.hist_off + 8u * L.cstride * L.copies;
+}
 
 // Workgroup partial slots and result-ring entries per integral.
 constexpr int kMaxBlocks = 4096;
