@@ -199,6 +199,12 @@ int vegas_dump_weights(vegas_h h, int integrand_id, uint64_t seed, uint64_t firs
  * (256 threads, enough workgroups to fill the GPU). */
 int vegas_set_launch(vegas_h h, int max_blocks, int threads);
 
+/* vegas_run captures its sequence of iterations in a hipGraph the first time
+ * a configuration (integrand, parameters, precision, events, seed, iteration
+ * count, alpha, launch shape, stream, timing) is run and replays it after
+ * that; enable = 0 launches the kernels one by one instead. Default on. */
+int vegas_set_graph(vegas_h h, int enable);
+
 /* Kernel timing: enable != 0 records HIP events around every launch of the
  * iteration kernel on the handle's stream; *iterate_ms and *n_launches (may
  * be NULL) receive the summed duration and the launch count since the last

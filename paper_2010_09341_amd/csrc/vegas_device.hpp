@@ -284,11 +284,9 @@ __device__ inline void stage_grid(const void* rec, const LdsLayout& L, unsigned 
   } else {
     const Rec32* g = static_cast<const Rec32*>(rec);
     float2* ew = reinterpret_cast<float2*>(smem);
-    float2* lj = ew + cells;
     for (int i = threadIdx.x; i < cells; i += blockDim.x) {
       const Rec32 r = g[i];
       ew[i] = make_float2(r.e, r.w);
-      lj[i] = make_float2(r.l2j, 0.f);
     }
   }
   double* h = reinterpret_cast<double*>(smem + L.hist_off);
@@ -320,13 +318,13 @@ __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem,
 template <int D_T, int FID, int PREC>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
                                                int D, uint32_t nb, double nb_pow_d,
-                                               const unsigned char* lds, const LdsLayout& L,
+                                               float log2_nb_pow_d, const unsigned char* lds,
+                                               const LdsLayout& L,
                                                uint32_t hbase, const IntegrandArgs& P,
                                                uint32_t* hist) {
   using Dm = Dims<D_T>;
   const uint32_t n_lo = (uint32_t)n, n_hi = (uint32_t)(n >> 32);
   const uint32_t row = nb * 8u;
-  const uint32_t second = 8u * L.cells;
   if constexpr (PREC == kFp64) {
     double x[Dm::kMax];
     double jac = 1.0;
@@ -345,8 +343,8 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const double frac = fma((double)rem, 0x1p-32, 0x1p-33);
             const uint32_t a = (uint32_t)d * row + (k << 3);
             const double e = *static_cast<const double*>(__builtin_assume_aligned(lds + a, 8));
-            const double w =
-                *static_cast<const double*>(__builtin_assume_aligned(lds + a + second, 8));
+            const double w = *static_cast<const double*>(
+                __builtin_assume_aligned(lds + a + 8u * L.cells, 8));
             x[d] = fma(frac, w, e);
             jac *= w;
             hist[d] = hbase + a;
@@ -358,11 +356,15 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
     return integrand_f64<FID>(x, Dm::kMax, D_T > 0 ? D_T : D, P) * (jac * nb_pow_d);
   } else {
     float x[Dm::kMax];
+    // log2 J = sum over 4-dimension blocks of log2(prod of binary32 widths)
+    // + D log2(nb); a block product below the binary32 normal range is
+    // clamped there (such an event's Jacobian is negligible either way)
     float l2j = 0.f;
 #pragma unroll
     for (int j = 0; j < Dm::kBlocks; ++j) {
       if (Dm::on(4 * j, D)) {
         const Words4 r = philox4x32_10(n_lo, n_hi, t, (uint32_t)j, k0, k1);
+        float wprod = 1.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int d = 4 * j + i;
@@ -377,15 +379,15 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
                 __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u)) - 0x1.fffffep-1f;
             const uint32_t a = (uint32_t)d * row + (k << 3);
             const float2 ew = *static_cast<const float2*>(__builtin_assume_aligned(lds + a, 8));
-            const float lj =
-                *static_cast<const float*>(__builtin_assume_aligned(lds + a + second, 8));
             x[d] = fmaf(frac, ew.y, ew.x);
-            l2j += lj;
+            wprod *= ew.y;
             hist[d] = hbase + a;
           }
         }
+        l2j += __builtin_amdgcn_logf(fmaxf(wprod, 0x1p-126f));
       }
     }
+    l2j += log2_nb_pow_d;  // D log2(nb)
     const F32Val v = integrand_f32<FID>(x, Dm::kMax, D_T > 0 ? D_T : D, P);
     // w = f * 2^(log2 J + log2 f), the power split into a binary32 mantissa
     // in [1, 2) and an integer exponent applied in binary64.

@@ -23,6 +23,7 @@ struct IterArgsDev {
   uint64_t n_events;  // events of the iteration (dump: number of events to dump)
   uint64_t first;     // dump: index of the first event
   double nb_pow_d;    // nb^D, the constant factor of the Jacobian
+  float log2_nb_pow_d;
   LdsLayout lds;
   uint32_t seed_lo, seed_hi;
   int dim;
@@ -48,14 +49,16 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
   if constexpr (DUMP) {
     for (; n < a.n_events; n += stride)
       a.w_out[n] = event_weight<D_T, FID, PREC>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
-                                                a.nb, a.nb_pow_d, smem, L, hbase, P, hist);
+                                                a.nb, a.nb_pow_d, a.log2_nb_pow_d, smem, L, hbase, P,
+                                                hist);
     return;
   } else {
     double s1 = 0.0, s2 = 0.0;
     uint32_t bad = 0;
     for (; n < a.n_events; n += stride) {
       double w = event_weight<D_T, FID, PREC>(n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
-                                              a.nb_pow_d, smem, L, hbase, P, hist);
+                                              a.nb_pow_d, a.log2_nb_pow_d, smem, L, hbase, P,
+                                              hist);
       if (!__builtin_isfinite(w)) {
         ++bad;
         w = 0.0;

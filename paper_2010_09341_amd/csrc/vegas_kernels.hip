@@ -134,7 +134,9 @@ const void* iterate_kernel(int fid, int prec, int dim, bool dump) {
   }
 }
 
-size_t iterate_lds_bytes(int dim, int nb) { return lds_bytes(lds_layout(dim, nb)); }
+size_t iterate_lds_bytes(int dim, int nb, int prec) {
+  return lds_bytes(lds_layout(dim, nb, prec));
+}
 
 static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   IterArgsDev a;
@@ -150,7 +152,8 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.dim = g.dim;
   a.nb = (uint32_t)g.nb;
   a.nb_pow_d = pow((double)g.nb, (double)g.dim);
-  a.lds = lds_layout(g.dim, g.nb);
+  a.log2_nb_pow_d = (float)(g.dim * log2((double)g.nb));
+  a.lds = lds_layout(g.dim, g.nb, L.prec);
   return a;
 }
 
@@ -164,7 +167,7 @@ hipError_t launch_iterate(const DevGrid& g, const IterLaunch& L, const Integrand
   IntegrandArgs p = P;
   void* args[] = {&a, &p};
   return hipLaunchKernel(k, dim3(L.blocks), dim3(L.threads), args,
-                         iterate_lds_bytes(g.dim, g.nb), s);
+                         iterate_lds_bytes(g.dim, g.nb, L.prec), s);
 }
 
 hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,
@@ -179,7 +182,7 @@ hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArg
   int64_t blocks = (L.count + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;
   return hipLaunchKernel(k, dim3((unsigned)blocks), dim3(threads), args,
-                         iterate_lds_bytes(g.dim, g.nb), s);
+                         iterate_lds_bytes(g.dim, g.nb, L.prec), s);
 }
 
 hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, bool refine,

@@ -246,6 +246,22 @@ struct vegas_ctx {
   std::vector<hipEvent_t> events;
   double* dump_buf = nullptr;
   size_t dump_n = 0;
+  // hipGraph of the last vegas_run configuration
+  bool use_graph = true;
+  hipGraphExec_t graph = nullptr;
+  struct RunKey {
+    int fid, prec, n_iter, blocks, threads, timing;
+    int64_t n_events;
+    uint64_t seed;
+    double alpha;
+    hipStream_t stream;
+    std::vector<double> params;
+    bool operator==(const RunKey& o) const {
+      return fid == o.fid && prec == o.prec && n_iter == o.n_iter && blocks == o.blocks &&
+             threads == o.threads && timing == o.timing && n_events == o.n_events &&
+             seed == o.seed && alpha == o.alpha && stream == o.stream && params == o.params;
+    }
+  } graph_key{};
 };
 
 namespace {
@@ -301,7 +317,7 @@ hipError_t ensure_events(vegas_h h, size_t n) {
 int blocks_for(vegas_h h, int fid, int64_t n_events) {
   const void* k = iterate_kernel(fid, h->prec, h->dim, false);
   const int cap = h->max_blocks > 0 ? std::min(h->max_blocks, kMaxBlocks) : kMaxBlocks;
-  return default_blocks(k, h->threads, iterate_lds_bytes(h->dim, h->nb), n_events, cap);
+  return default_blocks(k, h->threads, iterate_lds_bytes(h->dim, h->nb, h->prec), n_events, cap);
 }
 
 // Enqueue iterate + finalize (+ refine) for one iteration; event slots 2i, 2i+1
@@ -387,6 +403,7 @@ int vegas_destroy(vegas_h h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   if (h->dump_buf) (void)hipFree(h->dump_buf);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->own_ws) (void)hipFree(h->own_ws);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
@@ -519,9 +536,44 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
   const int blocks = blocks_for(h, integrand_id, n_events);
   if (blocks < 1) return fail(h, hipErrorInvalidValue);
   if (h->timing) VEGAS_TRY(h, ensure_events(h, 2 * (size_t)n_iter));
-  for (int i = 0; i < n_iter; ++i)
-    VEGAS_TRY(h, enqueue_iteration(h, integrand_id, P, n_events, seed, blocks, i, i + 1 < n_iter,
-                                   alpha));
+  auto enqueue_all = [&]() -> hipError_t {
+    for (int i = 0; i < n_iter; ++i) {
+      hipError_t e = enqueue_iteration(h, integrand_id, P, n_events, seed, blocks, i,
+                                       i + 1 < n_iter, alpha);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  if (h->use_graph) {
+    // the iterations read and advance the iteration counter on the device, so
+    // one captured sequence serves every run of the same configuration
+    vegas_ctx::RunKey key{integrand_id, h->prec, n_iter, blocks, h->threads, h->timing ? 1 : 0,
+                          n_events, seed, alpha, h->stream, h->params[integrand_id]};
+    if (!h->graph || !(key == h->graph_key)) {
+      if (h->graph) {
+        VEGAS_TRY(h, hipGraphExecDestroy(h->graph));
+        h->graph = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      VEGAS_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      const hipError_t ce = enqueue_all();
+      const hipError_t ee = hipStreamEndCapture(h->stream, &g);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(h, ce != hipSuccess ? ce : ee);
+      }
+      const hipError_t ie = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        h->graph = nullptr;
+        return fail(h, ie);
+      }
+      h->graph_key = key;
+    }
+    VEGAS_TRY(h, hipGraphLaunch(h->graph, h->stream));
+  } else {
+    VEGAS_TRY(h, enqueue_all());
+  }
   VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.results, 4 * sizeof(double) * kRing,
                               hipMemcpyDeviceToHost, h->stream));
   VEGAS_TRY(h, hipStreamSynchronize(h->stream));
@@ -679,6 +731,13 @@ int vegas_set_launch(vegas_h h, int max_blocks, int threads) {
   if (threads != 64 && threads != 128 && threads != 256) return VEGAS_EINVAL;
   h->max_blocks = max_blocks;
   h->threads = threads;
+  return VEGAS_OK;
+}
+
+int vegas_set_graph(vegas_h h, int enable) {
+  int rc = ready(h);
+  if (rc) return rc;
+  h->use_graph = enable != 0;
   return VEGAS_OK;
 }
 

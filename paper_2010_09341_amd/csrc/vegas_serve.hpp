@@ -35,6 +35,8 @@ struct SlotDev {
   int ring;
   double nb_pow_d;
   double alpha;
+  float log2_nb_pow_d;
+  int pad;
   IntegrandArgs P;
 };
 

@@ -154,7 +154,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
     const int pc = q->r.prec == VEGAS_FP64 ? 0 : 1;
     const int dc = dim <= 16 ? 0 : 1;
     for (uint32_t c = 0; c < q->n_chunks; ++c) work[pc][dc].push_back(WorkItem{(uint32_t)q->slot, c});
-    max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(lds_layout(dim, nb)));
+    max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(lds_layout(dim, nb, q->r.prec)));
     const uint32_t refine = q->iters + 1 < q->r.n_iter ? 1u : 0u;
     fin_items.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
     for (int d = 0; d < dim; ++d) fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine});
@@ -248,6 +248,7 @@ void vegas_srv::run() {
         S.ring = q->r.n_iter;
         S.nb_pow_d = std::pow((double)q->r.n_bins, (double)q->r.dim);
         S.alpha = q->r.alpha;
+        S.log2_nb_pow_d = (float)(q->r.dim * std::log2((double)q->r.n_bins));
         S.P = q->P;
         slots_pin[q->slot] = S;
       }

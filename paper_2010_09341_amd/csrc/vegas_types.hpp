@@ -41,13 +41,13 @@ struct alignas(16) Rec32 {
 
 // LDS layout of the iteration kernels' workgroups (cells = dim * nb, cell
 // (d, k) = d * nb + k):
-//   [0, 8 cells)        FP64: e_k            FP32: {e_k, w_k} (binary32 pair)
-//   [8 cells, 16 cells) FP64: w_k            FP32: log2(nb w_k) in the low word
-//   [hist_off, ...)     `copies` histograms of w^2 (binary64), copy stride
-//                       cstride entries; lane l adds into copy l % copies
-// Every random access is 8 bytes at an 8-byte stride (4 bytes for the
-// binary32 log2), which keeps LDS bank conflicts low; the histogram copies
-// split the lanes of a wave that hit the same bin. At most 64 KiB.
+//   FP64: [0, 8 cells) e_k, [8 cells, 16 cells) w_k = e_{k+1} - e_k
+//   FP32: [0, 8 cells) {e_k, w_k} as a binary32 pair
+//   then `copies` histograms of w^2 (binary64), copy stride cstride entries;
+//   lane l adds into copy l % copies.
+// Every random access is 8 bytes at an 8-byte stride, which keeps LDS bank
+// conflicts low; the histogram copies split the lanes of a wave that hit the
+// same bin. At most 64 KiB.
 struct LdsLayout {
   uint32_t cells;
   uint32_t hist_off;  // bytes
@@ -55,10 +55,10 @@ struct LdsLayout {
   uint32_t copies;    // 1, 2 or 4
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int dim, int nb) {
+__host__ __device__ inline LdsLayout lds_layout(int dim, int nb, int prec) {
   LdsLayout L;
   L.cells = (uint32_t)(dim * nb);
-  L.hist_off = 16u * L.cells;
+  L.hist_off = (prec == kFp64 ? 16u : 8u) * L.cells;
   L.cstride = L.cells + 4u;
   const uint32_t budget = 65536u;
   L.copies = 4u;

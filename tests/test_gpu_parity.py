@@ -276,3 +276,30 @@ def test_state_machine(vg):
     bad[1, 4] = bad[1, 5]
     with pytest.raises(vg.VegasError):
         vg.vegas_set_grid(h, bad)
+
+
+def test_graph_replays_match_eager(vg):
+    """vegas_run through its captured hipGraph, replayed several times with
+    eager work and synchronisations in between, equals eager launches."""
+    def make(graph):
+        h = vg.vegas_create(8, 50)
+        vg.vegas_set_params(h, W.F_GAUSS, [0.1])
+        vg.vegas_set_precision(h, W.FP32_EVAL)
+        vg.vegas_set_graph(h, graph)
+        return h
+    hg, he, other = make(True), make(False), make(False)
+    for rep in range(4):
+        vg.vegas_reset(hg)
+        vg.vegas_reset(he)
+        I_g, s_g = vg.vegas_run(hg, W.F_GAUSS, 300_000, 5, 6, 1.5)
+        vg.vegas_iterate(other, W.F_GAUSS, 100_000, rep)  # unrelated eager work
+        I_e, s_e = vg.vegas_run(he, W.F_GAUSS, 300_000, 5, 6, 1.5)
+        assert np.all(np.abs(I_g - I_e) <= 1e-13 * np.abs(I_e)), (rep, I_g - I_e)
+        assert np.all(np.abs(s_g - s_e) <= 1e-11 * np.abs(s_e))
+        assert vg.vegas_get_iteration(hg) == 6
+    # timing inside the captured sequence
+    vg.vegas_timing(hg, True, True)
+    vg.vegas_reset(hg)
+    vg.vegas_run(hg, W.F_GAUSS, 300_000, 5, 6, 1.5)
+    ms, n = vg.vegas_timing(hg, False)
+    assert n == 6 and ms > 0
