@@ -126,12 +126,20 @@ def main():
         for _ in range(args.warmup):
             step(h)
         torch.cuda.synchronize()
-        vg.vegas_timing(h, True, True)
+        # throughput: whole runs, each a replay of the captured iteration graph
         t0 = time.perf_counter()
         for _ in range(args.steps):
             I_t, s_t, comb = step(h)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # kernel durations: the same steps launched one by one with HIP events
+        # around every iteration kernel on the handle's stream
+        vg.vegas_timing(h, True, True)
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step(h)
+        torch.cuda.synchronize()
+        dt_eager = time.perf_counter() - t1
         k_ms, k_n = vg.vegas_timing(h, False)
         # per-iteration latency: one synchronous vegas_iterate (launch, kernels,
         # 32-byte result copy, synchronisation) on the adapted grid
@@ -140,9 +148,10 @@ def main():
             a = time.perf_counter()
             vg.vegas_iterate(h, wl.fid, wl.n_events, wl.seed)
             lat.append(time.perf_counter() - a)
-        log(f"prec={prec}: {dt / args.steps * 1e3:.3f} ms/step, latency p50 "
-            f"{pct(lat, 50) * 1e3:.3f} ms")
-        results[prec] = dict(dt=dt, I_t=I_t, s_t=s_t, comb=comb, k_ms=k_ms, k_n=k_n, lat=lat)
+        log(f"prec={prec}: {dt / args.steps * 1e3:.3f} ms/step (eager {dt_eager / args.steps * 1e3:.3f}), "
+            f"kernel {k_ms / max(k_n, 1) * 1e3:.1f} us, latency p50 {pct(lat, 50) * 1e3:.3f} ms")
+        results[prec] = dict(dt=dt, dt_eager=dt_eager, I_t=I_t, s_t=s_t, comb=comb, k_ms=k_ms,
+                             k_n=k_n, lat=lat)
         del h
 
     r32, r64 = results[W.FP32_EVAL], results[W.FP64]
@@ -169,6 +178,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": r32["dt"] / args.steps * 1e3,
+        "ms_per_step_eager_launches": r32["dt_eager"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -201,8 +201,10 @@ int vegas_set_launch(vegas_h h, int max_blocks, int threads);
 
 /* vegas_run captures its sequence of iterations in a hipGraph the first time
  * a configuration (integrand, parameters, precision, events, seed, iteration
- * count, alpha, launch shape, stream, timing) is run and replays it after
- * that; enable = 0 launches the kernels one by one instead. Default on. */
+ * count, alpha, launch shape, stream) is run and replays it after that;
+ * enable = 0 launches the kernels one by one instead. Default on. While
+ * kernel timing (vegas_timing) is enabled, kernels are launched one by one so
+ * that HIP events can bracket each iteration kernel. */
 int vegas_set_graph(vegas_h h, int enable);
 
 /* Kernel timing: enable != 0 records HIP events around every launch of the

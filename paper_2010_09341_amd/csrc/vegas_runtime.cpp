@@ -544,10 +544,10 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
     }
     return hipSuccess;
   };
-  if (h->use_graph) {
+  if (h->use_graph && !h->timing) {
     // the iterations read and advance the iteration counter on the device, so
     // one captured sequence serves every run of the same configuration
-    vegas_ctx::RunKey key{integrand_id, h->prec, n_iter, blocks, h->threads, h->timing ? 1 : 0,
+    vegas_ctx::RunKey key{integrand_id, h->prec, n_iter, blocks, h->threads, 0,
                           n_events, seed, alpha, h->stream, h->params[integrand_id]};
     if (!h->graph || !(key == h->graph_key)) {
       if (h->graph) {

@@ -297,9 +297,10 @@ def test_graph_replays_match_eager(vg):
         assert np.all(np.abs(I_g - I_e) <= 1e-13 * np.abs(I_e)), (rep, I_g - I_e)
         assert np.all(np.abs(s_g - s_e) <= 1e-11 * np.abs(s_e))
         assert vg.vegas_get_iteration(hg) == 6
-    # timing inside the captured sequence
+    # with kernel timing on, the run launches eagerly and times each iteration
     vg.vegas_timing(hg, True, True)
     vg.vegas_reset(hg)
-    vg.vegas_run(hg, W.F_GAUSS, 300_000, 5, 6, 1.5)
+    I_t, _ = vg.vegas_run(hg, W.F_GAUSS, 300_000, 5, 6, 1.5)
     ms, n = vg.vegas_timing(hg, False)
     assert n == 6 and ms > 0
+    assert np.all(np.abs(I_t - I_e) <= 1e-13 * np.abs(I_e))
