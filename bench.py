@@ -25,10 +25,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes issue one full-rate VALU operation per lane per
-# clock at 2.4 GHz. A quarter-rate operation (64-bit integer multiply-add,
-# binary32 transcendentals) occupies four such lane slots.
-PEAK_VALU_SLOTS = 256 * 64 * 2.4e9  # 3.93e13 lane slots/s
+# MI355X vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes, one VALU
+# instruction per lane per clock at 2.4 GHz (a wave64 instruction occupies its
+# SIMD for 4 clocks) = 3.93e13 lane-instructions/s. Measured on gfx950: the
+# 32x32->64 multiply-add and binary64 fma issue at about this rate.
+PEAK_VALU_SLOTS = 256 * 64 * 2.4e9
 PEAK_FP32_FLOPS = 157.3e12
 
 
@@ -36,33 +37,67 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def alg_slots_per_event(dim: int, nblk: int, prec: int, fid: int) -> float:
-    """Algorithmic VALU lane slots per event for the Gaussian workloads.
+def alg_valu_per_event(dim: int, prec: int) -> int:
+    """VALU lane-instructions of one event of the Gaussian integrand: the
+    minimal gfx950 instruction sequence of the method, counted operation by
+    operation (issued instructions are measured separately with
+    SQ_INSTS_VALU; the difference is compiler overhead).
 
-    Philox4x32-10: 10 rounds x (2 mul 32x32->64 at 4 slots + 4 xor) = 120.
-    Map per dimension: mul 32x32->64 (4) + fraction (2) + fma (1) + Jacobian
-    accumulation (1, FP32 log-sum / 2 FP64 multiplies) + LDS address (1).
-    Gaussian per dimension: subtract + fma (2). Weight: FP32 fma, floor,
-    subtract, exp2 (4), convert, ldexp, multiply (10); FP64 exp ~ 24.
-    Moments: add, fma, add (3). Histogram: address per dimension (1).
+      Philox4x32-10 per 4 dimensions: 10 rounds x (2 v_mad_u64_u32 + 2
+        three-input xor v_bitop3) = 40 (key schedule on the scalar unit)
+      event index and loop: 64-bit add (2) + compare (1) = 3
+      map per dimension: 32x32->64 product giving bin and remainder (1),
+        fraction (FP32: alignbit + subtract; FP64: convert + fma) (2), LDS
+        address (1), x = fma (1), Jacobian multiply (1), histogram address
+        (1) = 7; FP32 also max + log2 per 4 dimensions (2)
+      Gaussian per dimension: subtract + fma = 2
+      weight: FP32 log2 split (add, fma, floor, subtract, exp2 counted as 2,
+        two converts, ldexp) = 9; FP64 exp (range reduction and degree-11
+        polynomial, about 22) + the Jacobian constant and product (2) = 24
+      non-finite check (class, two selects, count) = 3; moments (w^2, two
+        adds) = 3
     """
-    if fid != 2:
-        return float("nan")
-    philox = nblk * 120
-    if prec == 1:
-        per_dim = 4 + 2 + 1 + 1 + 1 + 2 + 1
-        tail = 10
-    else:
-        per_dim = 4 + 2 + 1 + 2 + 1 + 2 + 1
-        tail = 24 + 2
-    return philox + dim * per_dim + tail + 3
+    blocks = (dim + 3) // 4
+    n = 40 * blocks + 3 + 7 * dim + 2 * dim + 3 + 3
+    n += (2 * blocks + 9) if prec == 1 else 24
+    return n
 
 
 def fp32_flops_per_event(dim: int) -> float:
     """Binary32 floating-point operations of the FP32-eval Gaussian per event
-    (fma = 2): map fma (2) + log-sum add (1) + subtract and fma (3) per
-    dimension, and the weight's fma, subtract, exp2 (3)."""
-    return dim * 6 + 3
+    (fma = 2): the fraction subtract (1), map fma (2), width multiply (1),
+    subtract and fma (3) per dimension, and the weight's fma, subtract, exp2
+    (4)."""
+    return dim * 7 + 4
+
+
+KERNEL_SOURCES = ("vegas_device.hpp", "vegas_iterate.hpp", "vegas_types.hpp", "iter_gauss.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_iterate_gauss8d_fp32eval.md")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_09341_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the iteration kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None if the kernel sources changed since those counters were taken."""
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]{16})", text)
+    m_b = re.search(r"HBM traffic per launch \(bytes\): ([0-9.e+]+)", text)
+    if not m_hash or not m_b or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_b.group(1))
 
 
 def pct(a, q):
@@ -164,10 +199,10 @@ def main():
     # roofline of the iteration kernel (FP32-eval), from HIP events around
     # every launch of it inside the timed steps
     k_avg_s = r32["k_ms"] / max(r32["k_n"], 1) * 1e-3
-    slots = alg_slots_per_event(wl.dim, nblk, W.FP32_EVAL, wl.fid)
+    slots = alg_valu_per_event(wl.dim, W.FP32_EVAL)
     achieved = slots * wl.n_events / k_avg_s
     k64_avg_s = r64["k_ms"] / max(r64["k_n"], 1) * 1e-3
-    slots64 = alg_slots_per_event(wl.dim, nblk, W.FP64, wl.fid)
+    slots64 = alg_valu_per_event(wl.dim, W.FP64)
 
     out = {
         "metric": "Vegas events/sec at matched sigma (FP32-eval vs FP64) on 1 GPU; "
@@ -208,10 +243,10 @@ def main():
             "kernel": f"k_iterate<{nblk},gauss,fp32-eval>",
             "achieved": achieved / 1e12,
             "peak": PEAK_VALU_SLOTS / 1e12,
-            "unit": "T VALU lane-slots/s",
+            "unit": "T VALU lane-instructions/s",
             "frac": achieved / PEAK_VALU_SLOTS,
-            "traffic": None,
-            "slots_per_event": slots,
+            "traffic": traffic_from_profile(),
+            "valu_per_event_algorithmic": slots,
             "avg_launch_us": k_avg_s * 1e6,
             "launches": r32["k_n"],
             "fp32_flop_frac_of_157TF": fp32_flops_per_event(wl.dim) * wl.n_events / k_avg_s
