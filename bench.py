@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times, so that a "
                          "counter run can scale FETCH_SIZE/WRITE_SIZE by a known size")
@@ -264,12 +265,80 @@ def main():
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, r64["I_t"], r64["s_t"])
     if not args.no_serving:
-        try:
-            from paper_2010_09341_amd import serving_bench
-            out["serving"] = serving_bench.run_quick()
-        except (ImportError, AttributeError):
-            pass
+        out["serving"] = serving_section(vg, W, args.serving_requests)
     print(json.dumps(out))
+
+
+def replay(vg, W, trace, rate, max_slots, budget=4 << 30):
+    """Submit the trace at `rate` requests/s (inf: all at once) to a server
+    with `max_slots` slots; returns latency percentiles and throughput."""
+    import threading
+    srv = vg.vegas_server_create(budget, max_slots)
+    # warm the server's kernels outside the measurement
+    warm = vg.vegas_server_submit(srv, 3, 20, W.F_GAUSS, [0.2], 10_000, 2, 1.5, 0)
+    vg.vegas_server_wait(srv, warm)
+    base = trace[0].arrival_s
+    scale = 0.0 if math.isinf(rate) else 200.0 / rate
+    tickets = [None] * len(trace)
+    t0 = time.perf_counter()
+
+    def submit():
+        for i, r in enumerate(trace):
+            due = t0 + (r.arrival_s - base) * scale
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                time.sleep(min(due - now, 0.001) if due - now > 0.002 else 0)
+            tickets[i] = vg.vegas_server_submit(srv, r.dim, r.nb, r.fid, r.params, r.n_events,
+                                                r.n_iter, r.alpha, r.seed, r.prec)
+
+    th = threading.Thread(target=submit)
+    th.start()
+    lat = []
+    for i in range(len(trace)):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        _, _, _, l = vg.vegas_server_wait(srv, tickets[i])
+        lat.append(l)
+    t_end = time.perf_counter()
+    th.join()
+    done, events, items, peak = vg.vegas_server_stats(srv)
+    vg.vegas_server_destroy(srv)
+    ev = sum(r.n_events * r.n_iter for r in trace)
+    return {"rate_per_s": rate if not math.isinf(rate) else "closed-loop",
+            "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3,
+            "mean_ms": float(np.mean(lat)) * 1e3, "events_per_s": ev / (t_end - t0),
+            "makespan_s": t_end - t0, "peak_concurrent": peak}
+
+
+def serving_section(vg, W, n_requests):
+    """The serving stream (1000 Poisson arrivals at 200/s, mixed integrals),
+    batched (up to 256 integrals at once) and one integral at a time, then a
+    rate sweep; throughput compared at the one-at-a-time p99 of 200/s."""
+    trace = W.serving_trace(n_requests, rate_per_s=200.0, seed=0)
+    res = {"trace": f"{n_requests} requests, Poisson arrivals at 200/s, dims U{{2..12}}, bins "
+                    "U{20..100}, events/iteration log-U[1e4, 1e7], 5-10 iterations, Gaussian or "
+                    "Breit-Wigner x flat, FP32-eval; trace seed 0",
+           "total_events": int(sum(r.n_events * r.n_iter for r in trace))}
+    modes = {"batched": 256, "one_at_a_time": 1}
+    rates = [200.0, 1000.0, 3000.0, 10000.0, float("inf")]
+    for mode, slots in modes.items():
+        rows = []
+        for rate in rates:
+            log(f"serving {mode} at {rate}/s")
+            rows.append(replay(vg, W, trace, rate, slots))
+        res[mode] = rows
+    slo = res["one_at_a_time"][0]["p99_ms"]
+    best = {}
+    for mode in modes:
+        ok = [r for r in res[mode] if r["p99_ms"] <= slo]
+        best[mode] = max((r["events_per_s"] for r in ok), default=0.0)
+    res["p99_slo_ms"] = slo
+    res["throughput_at_slo_events_per_s"] = best
+    res["batched_over_one_at_a_time_at_slo"] = (best["batched"] / best["one_at_a_time"]
+                                                if best["one_at_a_time"] > 0 else None)
+    return res
 
 
 def cpu_baseline(wl, gpu_I_t, gpu_s_t):
