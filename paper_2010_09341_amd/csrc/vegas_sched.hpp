@@ -121,11 +121,12 @@ class Admission {
   std::vector<int> free_slots_;
 };
 
-// Events per chunk for an integral of n events per iteration: about n/256,
+// Events per chunk for an integral of n events per iteration: about n/2048
+// (so that a large integral alone still gives every CU several workgroups),
 // a multiple of 256, between 4096 and 262144 (or `fixed` when non-zero).
 inline int64_t chunk_events(int64_t n, int64_t fixed) {
   if (fixed > 0) return fixed;
-  int64_t c = (n + 255) / 256;
+  int64_t c = (n + 2047) / 2048;
   c = (c + 255) / 256 * 256;
   return std::min<int64_t>(std::max<int64_t>(c, 4096), 262144);
 }
