@@ -315,21 +315,23 @@ def replay(vg, W, trace, rate, max_slots, budget=4 << 30):
 def serving_section(vg, W, n_requests):
     """The serving stream (1000 Poisson arrivals at 200/s, mixed integrals),
     batched (up to 256 integrals at once) and one integral at a time, then a
-    rate sweep; throughput compared at the one-at-a-time p99 of 200/s."""
+    rate sweep; the sustained throughput of each mode compared under a p99
+    objective of twice the one-at-a-time p99 at 200/s."""
     trace = W.serving_trace(n_requests, rate_per_s=200.0, seed=0)
     res = {"trace": f"{n_requests} requests, Poisson arrivals at 200/s, dims U{{2..12}}, bins "
                     "U{20..100}, events/iteration log-U[1e4, 1e7], 5-10 iterations, Gaussian or "
                     "Breit-Wigner x flat, FP32-eval; trace seed 0",
            "total_events": int(sum(r.n_events * r.n_iter for r in trace))}
     modes = {"batched": 256, "one_at_a_time": 1}
-    rates = [200.0, 1000.0, 3000.0, 10000.0, float("inf")]
+    rates = [200.0, 1000.0, 3000.0, 5000.0, 10000.0, float("inf")]
     for mode, slots in modes.items():
         rows = []
         for rate in rates:
             log(f"serving {mode} at {rate}/s")
             rows.append(replay(vg, W, trace, rate, slots))
         res[mode] = rows
-    slo = res["one_at_a_time"][0]["p99_ms"]
+    # SLO: twice the one-at-a-time p99 at the trace's own rate (200/s)
+    slo = 2.0 * res["one_at_a_time"][0]["p99_ms"]
     best = {}
     for mode in modes:
         ok = [r for r in res[mode] if r["p99_ms"] <= slo]

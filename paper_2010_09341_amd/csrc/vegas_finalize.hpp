@@ -39,6 +39,7 @@ __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, R
 // (and into out[0..3] if out is not null), then t += 1.
 __device__ inline void wg_moments(const double* partials, int n_partials, double N, uint32_t* t,
                                   double* results, int ring, double* out) {
+  const uint32_t tt = *t;  // issued together with the partial loads
   double s1 = 0.0, s2 = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < n_partials; i += 64) {
     s1 += partials[4 * i];
@@ -52,7 +53,6 @@ __device__ inline void wg_moments(const double* partials, int n_partials, double
     const double I = s1 / N;
     const double var = (s2 / N - I * I) / (N - 1.0);
     const double sig = sqrt(var > 0.0 ? var : 0.0);
-    const uint32_t tt = *t;
     double* r = results + 4 * (size_t)(tt % (uint32_t)ring);
     r[0] = I;
     r[1] = sig;
@@ -69,10 +69,15 @@ __device__ inline void wg_moments(const double* partials, int n_partials, double
 }
 
 // hist_row[k] = sum over copies c of copies[c][d][k] (fixed order); copies
-// zeroed; the row is also left in h_lds[0..nb).
+// zeroed; the row is also left in h_lds[0..nb). When eo_lds is not null the
+// dimension's edges erow[0..nb] are loaded into it in the same pass, so that
+// both sets of global loads are in flight together.
 __device__ inline void wg_reduce_hist(double* copies, double* hist_row, int cells, int d, int nb,
-                                      double* h_lds) {
-  for (int k = threadIdx.x; k < nb; k += 64) {
+                                      double* h_lds, const double* erow = nullptr,
+                                      double* eo_lds = nullptr) {
+  for (int k = threadIdx.x; k <= nb; k += 64) {
+    if (eo_lds) eo_lds[k] = erow[k];
+    if (k == nb) break;
     const size_t idx = (size_t)d * nb + k;
     double v = 0.0;
 #pragma unroll
@@ -99,15 +104,18 @@ __host__ __device__ constexpr int refine_lds_doubles(int nb) { return 3 * (nb + 
 //     the old bin k is the smallest with C_{k+1} >= j C_nb/nb (binary
 //     search), the position linear inside it;
 //  6. e_0 = 0, e_nb = 1; the records are rebuilt.
+// lds[0..nb] must already hold the old edges when edges_loaded is true.
 __device__ inline void wg_refine_dim(int nb, double alpha, double* erow, const double* h,
-                                     Rec64* rec64, Rec32* rec32, double* lds) {
+                                     Rec64* rec64, Rec32* rec32, double* lds,
+                                     bool edges_loaded = false) {
   const int lane = threadIdx.x;
   double* eo = lds;            // nb + 1
   double* en = eo + (nb + 1);  // nb + 1
   double* C = en + (nb + 1);   // nb + 1
   double* s = C + (nb + 1);    // nb
   double* r = s + nb;          // nb
-  for (int i = lane; i <= nb; i += 64) eo[i] = erow[i];
+  if (!edges_loaded)
+    for (int i = lane; i <= nb; i += 64) eo[i] = erow[i];
   for (int i = lane; i < nb; i += 64) {
     double v;
     if (i == 0)

@@ -58,10 +58,12 @@ __global__ __launch_bounds__(64) void k_finalize(FinArgs a) {
   const int d = blockIdx.x - 1;
   const int nb = a.nb;
   double* h = fsm;
-  wg_reduce_hist(a.copies, a.hist + (size_t)d * nb, a.dim * nb, d, nb, h);
+  double* erow = a.edges + (size_t)d * (nb + 1);
+  wg_reduce_hist(a.copies, a.hist + (size_t)d * nb, a.dim * nb, d, nb, h, erow,
+                 a.refine ? fsm + nb : nullptr);
   if (a.refine)
-    wg_refine_dim(nb, a.alpha, a.edges + (size_t)d * (nb + 1), h, a.rec64 + (size_t)d * nb,
-                  a.rec32 + (size_t)d * nb, fsm + nb);
+    wg_refine_dim(nb, a.alpha, erow, h, a.rec64 + (size_t)d * nb, a.rec32 + (size_t)d * nb,
+                  fsm + nb, true);
 }
 
 // refine from the stored histogram (after the histogram was set by the host)

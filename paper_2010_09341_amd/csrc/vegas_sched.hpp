@@ -123,12 +123,13 @@ class Admission {
 
 // Events per chunk for an integral of n events per iteration: about n/2048
 // (so that a large integral alone still gives every CU several workgroups),
-// a multiple of 256, between 4096 and 262144 (or `fixed` when non-zero).
+// a multiple of 256, between 2048 (so that a small integral still spreads
+// over several workgroups) and 262144 (or `fixed` when non-zero).
 inline int64_t chunk_events(int64_t n, int64_t fixed) {
   if (fixed > 0) return fixed;
   int64_t c = (n + 2047) / 2048;
   c = (c + 255) / 256 * 256;
-  return std::min<int64_t>(std::max<int64_t>(c, 4096), 262144);
+  return std::min<int64_t>(std::max<int64_t>(c, 2048), 262144);
 }
 
 }  // namespace vegas

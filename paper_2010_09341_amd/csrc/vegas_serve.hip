@@ -112,10 +112,12 @@ __global__ __launch_bounds__(64) void k_serve_finalize(const SlotDev* slots, con
     return;
   }
   const int d = f.role;
-  wg_reduce_hist(S.copies, S.hist + (size_t)d * nb, S.dim * nb, d, nb, fsm);
+  double* erow = S.edges + (size_t)d * (nb + 1);
+  wg_reduce_hist(S.copies, S.hist + (size_t)d * nb, S.dim * nb, d, nb, fsm, erow,
+                 f.refine ? fsm + nb : nullptr);
   if (f.refine)
-    wg_refine_dim(nb, S.alpha, S.edges + (size_t)d * (nb + 1), fsm, S.rec64 + (size_t)d * nb,
-                  S.rec32 + (size_t)d * nb, fsm + nb);
+    wg_refine_dim(nb, S.alpha, erow, fsm, S.rec64 + (size_t)d * nb, S.rec32 + (size_t)d * nb,
+                  fsm + nb, true);
 }
 
 __global__ __launch_bounds__(64) void k_serve_init(const SlotDev* slots, const FinItem* items,

@@ -85,13 +85,13 @@ static void admission() {
 }
 
 static void chunks() {
-  CHECK(vegas::chunk_events(10000, 0) == 4096);
+  CHECK(vegas::chunk_events(10000, 0) == 2048);
   CHECK(vegas::chunk_events(10000000, 0) == 5120);
   CHECK(vegas::chunk_events(100000000000LL, 0) == 262144);
   CHECK(vegas::chunk_events(123, 777) == 777);
   for (long long n : {2LL, 4097LL, 1000003LL, 123456789LL}) {
     const long long c = vegas::chunk_events(n, 0);
-    CHECK(c % 256 == 0 && c >= 4096 && c <= 262144);
+    CHECK(c % 256 == 0 && c >= 2048 && c <= 262144);
   }
 }
 
