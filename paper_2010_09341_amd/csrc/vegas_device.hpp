@@ -283,11 +283,8 @@ __device__ inline void stage_grid(const void* rec, const LdsLayout& L, unsigned 
     }
   } else {
     const Rec32* g = static_cast<const Rec32*>(rec);
-    float2* ew = reinterpret_cast<float2*>(smem);
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-      const Rec32 r = g[i];
-      ew[i] = make_float2(r.e, r.w);
-    }
+    Rec32* ew = reinterpret_cast<Rec32*>(smem);
+    for (int i = threadIdx.x; i < cells; i += blockDim.x) ew[i] = g[i];
   }
   double* h = reinterpret_cast<double*>(smem + L.hist_off);
   const int nh = (int)(L.cstride * L.copies);
@@ -315,13 +312,13 @@ __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem,
 // hist[d], the LDS byte address of the histogram entry that dimension d fell
 // into (in this lane's copy).
 // ---------------------------------------------------------------------------
-template <int D_T, int FID, int PREC>
+template <int D_T, int FID, int PREC, bool RG = false>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
                                                int D, uint32_t nb, double nb_pow_d,
                                                float log2_nb_pow_d, const unsigned char* lds,
                                                const LdsLayout& L,
                                                uint32_t hbase, const IntegrandArgs& P,
-                                               uint32_t* hist) {
+                                               uint32_t* hist, const Rec32* grec = nullptr) {
   using Dm = Dims<D_T>;
   const uint32_t n_lo = (uint32_t)n, n_hi = (uint32_t)(n >> 32);
   const uint32_t row = nb * 8u;
@@ -378,9 +375,13 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const float frac =
                 __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u)) - 0x1.fffffep-1f;
             const uint32_t a = (uint32_t)d * row + (k << 3);
-            const float2 ew = *static_cast<const float2*>(__builtin_assume_aligned(lds + a, 8));
-            x[d] = fmaf(frac, ew.y, ew.x);
-            wprod *= ew.y;
+            Rec32 ew;
+            if constexpr (RG)
+              ew = grec[(uint32_t)d * nb + k];
+            else
+              ew = *static_cast<const Rec32*>(__builtin_assume_aligned(lds + a, 8));
+            x[d] = fmaf(frac, ew.w, ew.e);
+            wprod *= ew.w;
             hist[d] = hbase + a;
           }
         }

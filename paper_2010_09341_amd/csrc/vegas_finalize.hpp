@@ -22,15 +22,12 @@ __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, R
   for (int k = threadIdx.x; k < nb; k += 64) {
     const double lo = e[k], hi = e[k + 1];
     rec64[k] = Rec64{lo, hi - lo};
+    // binary32 record: the rounded lower edge and the binary32 difference of
+    // the rounded edges, so that e + w lands on the rounded upper edge
     const float lo32 = (float)lo, hi32 = (float)hi;
-    const double w32 = (double)hi32 - (double)lo32;  // exact
-    const double jac = (double)nb * w32;
     Rec32 r;
     r.e = lo32;
-    r.w = (float)w32;
-    // a bin narrower than binary32 resolution carries a vanishing Jacobian
-    r.l2j = (float)log2(jac > 0x1p-1000 ? jac : 0x1p-1000);
-    r.pad = 0.f;
+    r.w = (float)((double)hi32 - (double)lo32);
     rec32[k] = r;
   }
 }

@@ -15,6 +15,7 @@
 // ALU issue (integer multiplies of Philox, map and integrand arithmetic).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "vegas_device.hpp"
@@ -156,12 +157,15 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.nb_pow_d = pow((double)g.nb, (double)g.dim);
   a.log2_nb_pow_d = (float)(g.dim * log2((double)g.nb));
   a.lds = lds_layout(g.dim, g.nb, L.prec);
+  a.rec32g = static_cast<const Rec32*>(g.rec32);
   return a;
 }
 
 hipError_t launch_iterate(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,
                           hipStream_t s) {
   const void* k = iterate_kernel(L.fid, L.prec, g.dim, false);
+  static const bool rg = getenv("VEGAS_EXPERIMENT_RECGLOBAL") != nullptr;
+  if (rg && L.fid == kGauss && L.prec == kFp32Eval && g.dim == 8) k = iterate_kernel_gauss8_rg();
   if (!k || L.blocks < 1 || L.blocks > g.max_blocks || L.threads < 64 ||
       L.threads > kIterThreadsMax || (L.threads & 63))
     return hipErrorInvalidValue;

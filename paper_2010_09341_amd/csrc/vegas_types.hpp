@@ -29,14 +29,14 @@ struct IntegrandArgs {
 
 // Grid record of bin k in dimension d.
 //   FP64: {e_k, e_{k+1} - e_k}
-//   FP32: {e_k, delta_k, log2(nb * delta_k), 0} with e_k rounded to binary32
-//         and delta_k the binary32 difference of the rounded edges, so that
-//         e_k + delta_k lands on the rounded e_{k+1}.
+//   FP32: {e_k, delta_k} with e_k rounded to binary32 and delta_k the
+//         binary32 difference of the rounded edges, so that e_k + delta_k
+//         lands on the rounded e_{k+1}.
 struct Rec64 {
   double e, w;
 };
-struct alignas(16) Rec32 {
-  float e, w, l2j, pad;
+struct alignas(8) Rec32 {
+  float e, w;
 };
 
 // LDS layout of the iteration kernels' workgroups (cells = dim * nb, cell
