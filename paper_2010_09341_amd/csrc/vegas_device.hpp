@@ -268,38 +268,22 @@ struct Dims {
   __device__ static constexpr bool on(int d, int D) { return D_T > 0 ? d < D_T : d < D; }
 };
 
-// Stage the grid records of the integral into LDS and zero the histograms.
-template <int PREC>
-__device__ inline void stage_grid(const void* rec, const LdsLayout& L, unsigned char* smem) {
-  const int cells = (int)L.cells;
-  if constexpr (PREC == kFp64) {
-    const Rec64* g = static_cast<const Rec64*>(rec);
-    double* e = reinterpret_cast<double*>(smem);
-    double* w = e + cells;
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-      const Rec64 r = g[i];
-      e[i] = r.e;
-      w[i] = r.w;
-    }
-  } else {
-    const Rec32* g = static_cast<const Rec32*>(rec);
-    Rec32* ew = reinterpret_cast<Rec32*>(smem);
-    for (int i = threadIdx.x; i < cells; i += blockDim.x) ew[i] = g[i];
-  }
-  double* h = reinterpret_cast<double*>(smem + L.hist_off);
+// Zero the workgroup's LDS histograms.
+__device__ inline void zero_hist(const LdsLayout& L, unsigned char* smem) {
+  double* h = reinterpret_cast<double*>(smem);
   const int nh = (int)(L.cstride * L.copies);
   for (int i = threadIdx.x; i < nh; i += blockDim.x) h[i] = 0.0;
 }
 
 // Byte address, in LDS, of this lane's histogram copy.
 __device__ inline uint32_t lane_hist_base(const LdsLayout& L) {
-  return L.hist_off + 8u * L.cstride * (threadIdx.x & (L.copies - 1u));
+  return 8u * L.cstride * (threadIdx.x & (L.copies - 1u));
 }
 
 // Add the LDS histogram copies of cell i and flush non-zero sums into dst
 // (global binary64 atomics). Needs a barrier before it.
 __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem, double* dst) {
-  const double* h = reinterpret_cast<const double*>(smem + L.hist_off);
+  const double* h = reinterpret_cast<const double*>(smem);
   for (int i = threadIdx.x; i < (int)L.cells; i += blockDim.x) {
     double v = h[i];
     for (uint32_t c = 1; c < L.copies; ++c) v += h[c * L.cstride + i];
@@ -308,20 +292,19 @@ __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem,
 }
 
 // ---------------------------------------------------------------------------
-// One event: draw, map, evaluate. Returns w = f(x) * J in binary64 and, in
-// hist[d], the LDS byte address of the histogram entry that dimension d fell
-// into (in this lane's copy).
+// One event: draw, map, evaluate. The grid records come from global memory
+// through the vector cache (a few KiB, resident after the first events).
+// Returns w = f(x) * J in binary64 and, in hist[d], the LDS byte address of
+// the histogram entry that dimension d fell into (in this lane's copy).
 // ---------------------------------------------------------------------------
-template <int D_T, int FID, int PREC, bool RG = false>
+template <int D_T, int FID, int PREC>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
                                                int D, uint32_t nb, double nb_pow_d,
-                                               float log2_nb_pow_d, const unsigned char* lds,
-                                               const LdsLayout& L,
+                                               float log2_nb_pow_d, const void* rec,
                                                uint32_t hbase, const IntegrandArgs& P,
-                                               uint32_t* hist, const Rec32* grec = nullptr) {
+                                               uint32_t* hist) {
   using Dm = Dims<D_T>;
   const uint32_t n_lo = (uint32_t)n, n_hi = (uint32_t)(n >> 32);
-  const uint32_t row = nb * 8u;
   if constexpr (PREC == kFp64) {
     double x[Dm::kMax];
     double jac = 1.0;
@@ -338,13 +321,11 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const uint32_t rem = (uint32_t)prod;
             // (rem + 1/2) 2^-32, exact in binary64
             const double frac = fma((double)rem, 0x1p-32, 0x1p-33);
-            const uint32_t a = (uint32_t)d * row + (k << 3);
-            const double e = *static_cast<const double*>(__builtin_assume_aligned(lds + a, 8));
-            const double w = *static_cast<const double*>(
-                __builtin_assume_aligned(lds + a + 8u * L.cells, 8));
-            x[d] = fma(frac, w, e);
-            jac *= w;
-            hist[d] = hbase + a;
+            const uint32_t cell = (uint32_t)d * nb + k;
+            const Rec64 g = static_cast<const Rec64*>(rec)[cell];
+            x[d] = fma(frac, g.w, g.e);
+            jac *= g.w;
+            hist[d] = hbase + (cell << 3);
           }
         }
       }
@@ -374,15 +355,11 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             // of a 2^-23 cell, exact in binary32
             const float frac =
                 __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u)) - 0x1.fffffep-1f;
-            const uint32_t a = (uint32_t)d * row + (k << 3);
-            Rec32 ew;
-            if constexpr (RG)
-              ew = grec[(uint32_t)d * nb + k];
-            else
-              ew = *static_cast<const Rec32*>(__builtin_assume_aligned(lds + a, 8));
-            x[d] = fmaf(frac, ew.w, ew.e);
-            wprod *= ew.w;
-            hist[d] = hbase + a;
+            const uint32_t cell = (uint32_t)d * nb + k;
+            const Rec32 g = static_cast<const Rec32*>(rec)[cell];
+            x[d] = fmaf(frac, g.w, g.e);
+            wprod *= g.w;
+            hist[d] = hbase + (cell << 3);
           }
         }
         l2j += __builtin_amdgcn_logf(fmaxf(wprod, 0x1p-126f));

@@ -25,7 +25,6 @@ struct IterArgsDev {
   double nb_pow_d;    // nb^D, the constant factor of the Jacobian
   float log2_nb_pow_d;
   LdsLayout lds;
-  const Rec32* rec32g;  // binary32 records read through the vector cache (RG variant)
   uint32_t seed_lo, seed_hi;
   int dim;
   uint32_t nb;
@@ -33,19 +32,15 @@ struct IterArgsDev {
 
 constexpr int kIterThreadsMax = 256;
 
-template <int D_T, int FID, int PREC, bool DUMP, bool RG = false>
+template <int D_T, int FID, int PREC, bool DUMP>
 __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, IntegrandArgs P) {
   extern __shared__ __align__(16) unsigned char smem[];
   using Dm = Dims<D_T>;
-  LdsLayout L = a.lds;
-  if constexpr (RG) {
-    L.hist_off = 0;
-    double* h = reinterpret_cast<double*>(smem);
-    for (int i = threadIdx.x; i < (int)(L.cstride * L.copies); i += blockDim.x) h[i] = 0.0;
-  } else {
-    stage_grid<PREC>(a.rec, L, smem);
+  const LdsLayout L = a.lds;
+  if constexpr (!DUMP) {
+    zero_hist(L, smem);
+    __syncthreads();
   }
-  __syncthreads();
 
   const uint32_t t = *a.t;
   const uint32_t hbase = lane_hist_base(L);
@@ -55,17 +50,16 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
 
   if constexpr (DUMP) {
     for (; n < a.n_events; n += stride)
-      a.w_out[n] = event_weight<D_T, FID, PREC, RG>(a.first + n, t, a.seed_lo, a.seed_hi,
-                                                    a.dim, a.nb, a.nb_pow_d, a.log2_nb_pow_d, smem,
-                                                    L, hbase, P, hist, a.rec32g);
+      a.w_out[n] = event_weight<D_T, FID, PREC>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
+                                                a.nb, a.nb_pow_d, a.log2_nb_pow_d, a.rec, hbase,
+                                                P, hist);
     return;
   } else {
     double s1 = 0.0, s2 = 0.0;
     uint32_t bad = 0;
     for (; n < a.n_events; n += stride) {
-      double w = event_weight<D_T, FID, PREC, RG>(n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
-                                                  a.nb_pow_d, a.log2_nb_pow_d, smem, L, hbase, P,
-                                                  hist, a.rec32g);
+      double w = event_weight<D_T, FID, PREC>(n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
+                                              a.nb_pow_d, a.log2_nb_pow_d, a.rec, hbase, P, hist);
       if (!__builtin_isfinite(w)) {
         ++bad;
         w = 0.0;
@@ -149,10 +143,6 @@ const void* pick_integrand(int prec, int dim, bool dump) {
   if (prec == kFp64) return dump ? pick_dims<FID, kFp64, true>(dim) : pick_dims<FID, kFp64, false>(dim);
   return dump ? pick_dims<FID, kFp32Eval, true>(dim) : pick_dims<FID, kFp32Eval, false>(dim);
 }
-
-// Binary32 8-D Gaussian with the grid records read through the vector cache
-// instead of LDS (a measured alternative of the default kernel).
-const void* iterate_kernel_gauss8_rg();
 
 // One per translation unit iter_*.hip.
 const void* iterate_kernel_const(int prec, int dim, bool dump);

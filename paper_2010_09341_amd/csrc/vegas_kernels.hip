@@ -15,7 +15,6 @@
 // ALU issue (integer multiplies of Philox, map and integrand arithmetic).
 #include <hip/hip_runtime.h>
 
-#include <cstdlib>
 #include <type_traits>
 
 #include "vegas_device.hpp"
@@ -137,9 +136,7 @@ const void* iterate_kernel(int fid, int prec, int dim, bool dump) {
   }
 }
 
-size_t iterate_lds_bytes(int dim, int nb, int prec) {
-  return lds_bytes(lds_layout(dim, nb, prec));
-}
+size_t iterate_lds_bytes(int dim, int nb) { return lds_bytes(lds_layout(dim, nb)); }
 
 static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   IterArgsDev a;
@@ -156,16 +153,13 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.nb = (uint32_t)g.nb;
   a.nb_pow_d = pow((double)g.nb, (double)g.dim);
   a.log2_nb_pow_d = (float)(g.dim * log2((double)g.nb));
-  a.lds = lds_layout(g.dim, g.nb, L.prec);
-  a.rec32g = static_cast<const Rec32*>(g.rec32);
+  a.lds = lds_layout(g.dim, g.nb);
   return a;
 }
 
 hipError_t launch_iterate(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,
                           hipStream_t s) {
   const void* k = iterate_kernel(L.fid, L.prec, g.dim, false);
-  static const bool rg = getenv("VEGAS_EXPERIMENT_RECGLOBAL") != nullptr;
-  if (rg && L.fid == kGauss && L.prec == kFp32Eval && g.dim == 8) k = iterate_kernel_gauss8_rg();
   if (!k || L.blocks < 1 || L.blocks > g.max_blocks || L.threads < 64 ||
       L.threads > kIterThreadsMax || (L.threads & 63))
     return hipErrorInvalidValue;
@@ -173,7 +167,7 @@ hipError_t launch_iterate(const DevGrid& g, const IterLaunch& L, const Integrand
   IntegrandArgs p = P;
   void* args[] = {&a, &p};
   return hipLaunchKernel(k, dim3(L.blocks), dim3(L.threads), args,
-                         iterate_lds_bytes(g.dim, g.nb, L.prec), s);
+                         iterate_lds_bytes(g.dim, g.nb), s);
 }
 
 hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,
@@ -188,7 +182,7 @@ hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArg
   int64_t blocks = (L.count + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;
   return hipLaunchKernel(k, dim3((unsigned)blocks), dim3(threads), args,
-                         iterate_lds_bytes(g.dim, g.nb, L.prec), s);
+                         iterate_lds_bytes(g.dim, g.nb), s);
 }
 
 hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, bool refine,

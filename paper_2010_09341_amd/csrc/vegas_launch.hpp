@@ -42,7 +42,7 @@ struct IterLaunch {
 // Iteration kernel (draw, map, evaluate, moments, histogram) for the given
 // integrand/precision/dimension; NULL if the combination does not exist.
 const void* iterate_kernel(int fid, int prec, int dim, bool dump);
-size_t iterate_lds_bytes(int dim, int nb, int prec);
+size_t iterate_lds_bytes(int dim, int nb);
 
 hipError_t launch_iterate(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,
                           hipStream_t s);

@@ -317,7 +317,7 @@ hipError_t ensure_events(vegas_h h, size_t n) {
 int blocks_for(vegas_h h, int fid, int64_t n_events) {
   const void* k = iterate_kernel(fid, h->prec, h->dim, false);
   const int cap = h->max_blocks > 0 ? std::min(h->max_blocks, kMaxBlocks) : kMaxBlocks;
-  return default_blocks(k, h->threads, iterate_lds_bytes(h->dim, h->nb, h->prec), n_events, cap);
+  return default_blocks(k, h->threads, iterate_lds_bytes(h->dim, h->nb), n_events, cap);
 }
 
 // Enqueue iterate + finalize (+ refine) for one iteration; event slots 2i, 2i+1

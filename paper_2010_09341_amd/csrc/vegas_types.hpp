@@ -39,35 +39,28 @@ struct alignas(8) Rec32 {
   float e, w;
 };
 
-// LDS layout of the iteration kernels' workgroups (cells = dim * nb, cell
-// (d, k) = d * nb + k):
-//   FP64: [0, 8 cells) e_k, [8 cells, 16 cells) w_k = e_{k+1} - e_k
-//   FP32: [0, 8 cells) {e_k, w_k} as a binary32 pair
-//   then `copies` histograms of w^2 (binary64), copy stride cstride entries;
-//   lane l adds into copy l % copies.
-// Every random access is 8 bytes at an 8-byte stride, which keeps LDS bank
-// conflicts low; the histogram copies split the lanes of a wave that hit the
-// same bin. At most 64 KiB.
+// LDS of the iteration kernels' workgroups: `copies` histograms of w^2
+// (binary64) for the cells (d, k) = d * nb + k, copy stride cstride entries;
+// lane l adds into copy l % copies, which splits the lanes of a wave that hit
+// the same bin. The grid records are read through the vector cache, so every
+// LDS access is a binary64 atomic at an 8-byte stride. At most 64 KiB.
 struct LdsLayout {
   uint32_t cells;
-  uint32_t hist_off;  // bytes
-  uint32_t cstride;   // histogram copy stride in entries
-  uint32_t copies;    // 1, 2 or 4
+  uint32_t cstride;  // histogram copy stride in entries
+  uint32_t copies;   // 1, 2 or 4
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int dim, int nb, int prec) {
+__host__ __device__ inline LdsLayout lds_layout(int dim, int nb) {
   LdsLayout L;
   L.cells = (uint32_t)(dim * nb);
-  L.hist_off = (prec == kFp64 ? 16u : 8u) * L.cells;
   L.cstride = L.cells + 4u;
-  const uint32_t budget = 65536u;
   L.copies = 4u;
-  while (L.copies > 1u && L.hist_off + 8u * L.cstride * L.copies > budget) L.copies >>= 1;
+  while (L.copies > 1u && 8u * L.cstride * L.copies > 65536u) L.copies >>= 1;
   return L;
 }
 
 __host__ __device__ inline uint32_t lds_bytes(const LdsLayout& L) {
-  return L.hist_off + 8u * L.cstride * L.copies;
+  return 8u * L.cstride * L.copies;
 }
 
 // Workgroup partial slots and result-ring entries per integral.
