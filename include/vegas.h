@@ -116,7 +116,9 @@ int vegas_create(int dim, int n_bins, vegas_h *out);
 int vegas_destroy(vegas_h h);
 
 /* Back to the state of vegas_create (uniform grid, t = 0, no history),
- * keeping parameters, precision, stream and workspace. */
+ * keeping parameters, precision, stream and workspace. The grid is rewritten
+ * by work queued on the handle's stream and not waited for; a device error
+ * shows at the next call that synchronises. */
 int vegas_reset(vegas_h h);
 
 /* Set the parameters used when integrand_id is evaluated (see the integrand

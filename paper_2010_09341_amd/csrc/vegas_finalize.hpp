@@ -37,11 +37,23 @@ __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, R
 __device__ inline void wg_moments(const double* partials, int n_partials, double N, uint32_t* t,
                                   double* results, int ring, double* out) {
   const uint32_t tt = *t;  // issued together with the partial loads
+  // The partials were written by workgroups on every XCD, so each load goes
+  // to memory: issue 8 independent 32-byte loads per lane before adding.
+  const double4* p4 = reinterpret_cast<const double4*>(partials);
   double s1 = 0.0, s2 = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < n_partials; i += 64) {
-    s1 += partials[4 * i];
-    s2 += partials[4 * i + 1];
-    b += partials[4 * i + 2];
+  for (int base = 0; base < n_partials; base += 8 * 64) {
+    double4 v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j * 64 + (int)threadIdx.x;
+      v[j] = i < n_partials ? p4[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      s1 += v[j].x;
+      s2 += v[j].y;
+      b += v[j].z;
+    }
   }
   s1 = wave_sum(s1);
   s2 = wave_sum(s2);

@@ -415,8 +415,8 @@ int vegas_reset(vegas_h h) {
   int rc = ready(h);
   if (rc) return rc;
   DeviceGuard dg(h->device);
+  // queued on the handle's stream ahead of any later work; not waited for
   VEGAS_TRY(h, launch_init_grid(h->g, h->stream));
-  VEGAS_TRY(h, hipStreamSynchronize(h->stream));
   h->t = 0;
   h->hist_valid = false;
   h->I_t.clear();
@@ -574,8 +574,16 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
   } else {
     VEGAS_TRY(h, enqueue_all());
   }
-  VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.results, 4 * sizeof(double) * kRing,
-                              hipMemcpyDeviceToHost, h->stream));
+  // copy back only this run's result entries (at most two pieces of the ring)
+  {
+    const size_t first = h->t % kRing;
+    const size_t n1 = std::min<size_t>((size_t)n_iter, kRing - first);
+    VEGAS_TRY(h, hipMemcpyAsync(h->pinned + 4 * first, h->g.results + 4 * first,
+                                4 * sizeof(double) * n1, hipMemcpyDeviceToHost, h->stream));
+    if (n1 < (size_t)n_iter)
+      VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.results, 4 * sizeof(double) * (n_iter - n1),
+                                  hipMemcpyDeviceToHost, h->stream));
+  }
   VEGAS_TRY(h, hipStreamSynchronize(h->stream));
   VEGAS_TRY(h, collect_timing(h, (size_t)n_iter));
   int64_t bad = 0;
