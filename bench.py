@@ -37,7 +37,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def alg_valu_per_event(dim: int, prec: int) -> int:
+def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
     """VALU lane-instructions of one event of the Gaussian integrand: the
     minimal gfx950 instruction sequence of the method, counted operation by
     operation (issued instructions are measured separately with
@@ -57,6 +57,8 @@ def alg_valu_per_event(dim: int, prec: int) -> int:
       non-finite check (class, two selects, count) = 3; moments (w^2, two
         adds) = 3
     """
+    if fid != 2:
+        return None  # counted for the Gaussian workloads only
     blocks = (dim + 3) // 4
     n = 40 * blocks + 3 + 7 * dim + 2 * dim + 3 + 3
     n += (2 * blocks + 9) if prec == 1 else 24
@@ -200,10 +202,10 @@ def main():
     # roofline of the iteration kernel (FP32-eval), from HIP events around
     # every launch of it inside the timed steps
     k_avg_s = r32["k_ms"] / max(r32["k_n"], 1) * 1e-3
-    slots = alg_valu_per_event(wl.dim, W.FP32_EVAL)
-    achieved = slots * wl.n_events / k_avg_s
+    slots = alg_valu_per_event(wl.dim, W.FP32_EVAL, wl.fid)
+    achieved = slots * wl.n_events / k_avg_s if slots else None
     k64_avg_s = r64["k_ms"] / max(r64["k_n"], 1) * 1e-3
-    slots64 = alg_valu_per_event(wl.dim, W.FP64)
+    slots64 = alg_valu_per_event(wl.dim, W.FP64, wl.fid)
 
     out = {
         "metric": "Vegas events/sec at matched sigma (FP32-eval vs FP64) on 1 GPU; "
@@ -241,21 +243,23 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": f"k_iterate<{nblk},gauss,fp32-eval>",
-            "achieved": achieved / 1e12,
+            "kernel": f"k_iterate<{wl.dim},{wl.name},fp32-eval>",
+            "achieved": achieved / 1e12 if achieved else None,
             "peak": PEAK_VALU_SLOTS / 1e12,
             "unit": "T VALU lane-instructions/s",
-            "frac": achieved / PEAK_VALU_SLOTS,
-            "traffic": traffic_from_profile(),
+            "frac": achieved / PEAK_VALU_SLOTS if achieved else None,
+            "traffic": traffic_from_profile() if wl.name == "gauss8d" else None,
             "valu_per_event_algorithmic": slots,
             "avg_launch_us": k_avg_s * 1e6,
             "launches": r32["k_n"],
-            "fp32_flop_frac_of_157TF": fp32_flops_per_event(wl.dim) * wl.n_events / k_avg_s
-            / PEAK_FP32_FLOPS,
+            "fp32_flop_frac_of_157TF": (fp32_flops_per_event(wl.dim) * wl.n_events / k_avg_s
+                                        / PEAK_FP32_FLOPS) if slots else None,
             "fp64_kernel": {"avg_launch_us": k64_avg_s * 1e6,
-                            "frac": slots64 * wl.n_events / k64_avg_s / PEAK_VALU_SLOTS},
+                            "frac": (slots64 * wl.n_events / k64_avg_s / PEAK_VALU_SLOTS)
+                            if slots64 else None},
         },
     }
+    out["latency_ms"]["gauss4d_fp64"] = small_latency(vg, W, args.latency_reps * 5)
     closed = W.gauss_closed_form(wl.dim, wl.params[0]) if wl.fid == W.F_GAUSS else None
     if closed is not None:
         out["closed_form"] = {"I": closed, "fp32_pull": (I32 - closed) / s32,
@@ -267,6 +271,22 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_section(vg, W, args.serving_requests)
     print(json.dumps(out))
+
+
+def small_latency(vg, W, reps):
+    """Per-iteration latency of the 4-D Gaussian parity workload (1e5 events,
+    FP64): synchronous vegas_iterate, launch to result on the host."""
+    wl = W.WORKLOADS["gauss4d"]
+    h = vg.vegas_create(wl.dim, wl.nb)
+    vg.vegas_set_params(h, wl.fid, wl.params)
+    vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+    lat = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        vg.vegas_iterate(h, wl.fid, wl.n_events, wl.seed)
+        lat.append(time.perf_counter() - a)
+    return {"what": f"one synchronous vegas_iterate of {wl.note}", "repeats": reps,
+            "p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3}
 
 
 def replay(vg, W, trace, rate, max_slots, budget=4 << 30):
