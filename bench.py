@@ -260,6 +260,7 @@ def main():
         },
     }
     out["latency_ms"]["gauss4d_fp64"] = small_latency(vg, W, args.latency_reps * 5)
+    out["events_limit_sweep"] = events_limit_sweep(vg, W, wl, max(3, args.steps // 4))
     closed = W.gauss_closed_form(wl.dim, wl.params[0]) if wl.fid == W.F_GAUSS else None
     if closed is not None:
         out["closed_form"] = {"I": closed, "fp32_pull": (I32 - closed) / s32,
@@ -271,6 +272,28 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_section(vg, W, args.serving_requests)
     print(json.dumps(out))
+
+
+def events_limit_sweep(vg, W, wl, steps):
+    """The paper's batch-size experiment (Fig. 2) on MI355X: a whole FP32-eval
+    run with at most a fraction of the events per kernel launch. Random
+    numbers are drawn on the device, so small batches cost launches, not
+    host-to-device transfers."""
+    rows = []
+    for frac in (0.02, 0.05, 0.1, 0.25, 0.5, 1.0):
+        h = vg.vegas_create(wl.dim, wl.nb)
+        vg.vegas_set_params(h, wl.fid, wl.params)
+        vg.vegas_set_precision(h, W.FP32_EVAL)
+        vg.vegas_set_events_limit(h, int(round(frac * wl.n_events)))
+        vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            vg.vegas_reset(h)
+            vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+        dt = (time.perf_counter() - t0) / steps
+        rows.append({"events_limit_fraction": frac, "launches_per_iteration": int(round(1 / frac)),
+                     "ms_per_run": dt * 1e3, "events_per_s": wl.n_events * wl.n_iter / dt})
+    return rows
 
 
 def small_latency(vg, W, reps):

@@ -201,9 +201,18 @@ int vegas_dump_weights(vegas_h h, int integrand_id, uint64_t seed, uint64_t firs
  * (256 threads, enough workgroups to fill the GPU). */
 int vegas_set_launch(vegas_h h, int max_blocks, int threads);
 
+/* The paper's events_limit (Sec. 3.1, and Fig. 2's batch-size experiment):
+ * at most `limit` events per launch of the iteration kernel; an iteration of
+ * n_events then runs as ceil(n_events/limit) launches on the handle's
+ * stream, each adding to the partial sums of the ones before in a fixed
+ * order. 0 (the default) runs every iteration as one launch. Random numbers
+ * are drawn on the device, so no batch crosses PCIe. limit >= 0. */
+int vegas_set_events_limit(vegas_h h, int64_t limit);
+
 /* vegas_run captures its sequence of iterations in a hipGraph the first time
  * a configuration (integrand, parameters, precision, events, seed, iteration
- * count, alpha, launch shape, stream) is run and replays it after that;
+ * count, alpha, launch shape, events limit, stream) is run and replays it
+ * after that;
  * enable = 0 launches the kernels one by one instead. Default on. While
  * kernel timing (vegas_timing) is enabled, kernels are launched one by one so
  * that HIP events can bracket each iteration kernel. */

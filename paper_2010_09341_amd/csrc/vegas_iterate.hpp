@@ -20,8 +20,9 @@ struct IterArgsDev {
   double* copies;
   double* partials;
   double* w_out;
-  uint64_t n_events;  // events of the iteration (dump: number of events to dump)
-  uint64_t first;     // dump: index of the first event
+  uint64_t n_events;  // events of this launch (dump: number of events to dump)
+  uint64_t first;     // index of the launch's first event
+  int accumulate;     // add to the workgroup partials of earlier launches
   double nb_pow_d;    // nb^D, the constant factor of the Jacobian
   float log2_nb_pow_d;
   LdsLayout lds;
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
     double s1 = 0.0, s2 = 0.0;
     uint32_t bad = 0;
     for (; n < a.n_events; n += stride) {
-      double w = event_weight<D_T, FID, PREC>(n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
+      double w = event_weight<D_T, FID, PREC>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
                                               a.nb_pow_d, a.log2_nb_pow_d, a.rec, hbase, P, hist);
       if (!__builtin_isfinite(w)) {
         ++bad;
@@ -93,10 +94,16 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
         ab += red[2][w];
       }
       double* p = a.partials + 4 * (size_t)blockIdx.x;
-      p[0] = a1;
-      p[1] = a2;
-      p[2] = ab;
-      p[3] = 0.0;
+      if (a.accumulate) {
+        p[0] += a1;
+        p[1] += a2;
+        p[2] += ab;
+      } else {
+        p[0] = a1;
+        p[1] = a2;
+        p[2] = ab;
+        p[3] = 0.0;
+      }
     }
     flush_hist(L, smem, a.copies + (size_t)(blockIdx.x % kHistCopies) * L.cells);
   }

@@ -147,6 +147,7 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.w_out = L.w_out;
   a.n_events = (uint64_t)L.n_events;
   a.first = L.first;
+  a.accumulate = L.accumulate ? 1 : 0;
   a.seed_lo = (uint32_t)L.seed;
   a.seed_hi = (uint32_t)(L.seed >> 32);
   a.dim = g.dim;

@@ -33,9 +33,12 @@ struct IterLaunch {
   uint64_t seed = 0;
   int blocks = 0;
   int threads = 256;
+  // a launch covering events first .. first+n_events-1 of the iteration, adding
+  // to the workgroup partials of earlier launches when accumulate is set
+  uint64_t first = 0;
+  bool accumulate = false;
   // dump mode only
   double* w_out = nullptr;
-  uint64_t first = 0;
   int64_t count = 0;
 };
 

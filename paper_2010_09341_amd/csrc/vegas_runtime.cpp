@@ -240,6 +240,7 @@ struct vegas_ctx {
   std::vector<double> params[VEGAS_N_INTEGRANDS];
   int max_blocks = 0;
   int threads = 256;
+  int64_t events_limit = 0;  // events per launch within an iteration (0: all)
   bool timing = false;
   double time_ms = 0.0;
   int64_t n_timed = 0;
@@ -251,7 +252,7 @@ struct vegas_ctx {
   hipGraphExec_t graph = nullptr;
   struct RunKey {
     int fid, prec, n_iter, blocks, threads, timing;
-    int64_t n_events;
+    int64_t n_events, events_limit;
     uint64_t seed;
     double alpha;
     hipStream_t stream;
@@ -259,6 +260,7 @@ struct vegas_ctx {
     bool operator==(const RunKey& o) const {
       return fid == o.fid && prec == o.prec && n_iter == o.n_iter && blocks == o.blocks &&
              threads == o.threads && timing == o.timing && n_events == o.n_events &&
+             events_limit == o.events_limit &&
              seed == o.seed && alpha == o.alpha && stream == o.stream && params == o.params;
     }
   } graph_key{};
@@ -320,21 +322,33 @@ int blocks_for(vegas_h h, int fid, int64_t n_events) {
   return default_blocks(k, h->threads, iterate_lds_bytes(h->dim, h->nb), n_events, cap);
 }
 
+// Events per launch of the iteration kernel.
+int64_t batch_events(vegas_h h, int64_t n_events) {
+  return h->events_limit > 0 && h->events_limit < n_events ? h->events_limit : n_events;
+}
+
 // Enqueue iterate + finalize (+ refine) for one iteration; event slots 2i, 2i+1
-// bracket the iteration kernel when timing is on.
+// bracket the iteration kernel launches when timing is on. With an events
+// limit the iteration's events go through several launches of at most that
+// many events, each adding to the workgroup partials of the previous ones.
 hipError_t enqueue_iteration(vegas_h h, int fid, const IntegrandArgs& P, int64_t n_events,
                              uint64_t seed, int blocks, size_t ev_slot, bool refine,
                              double alpha) {
+  const int64_t batch = batch_events(h, n_events);
   IterLaunch L;
   L.fid = fid;
   L.prec = h->prec;
-  L.n_events = n_events;
   L.seed = seed;
   L.blocks = blocks;
   L.threads = h->threads;
   hipError_t e;
   if (h->timing && (e = hipEventRecord(h->events[2 * ev_slot], h->stream)) != hipSuccess) return e;
-  if ((e = launch_iterate(h->g, L, P, h->stream)) != hipSuccess) return e;
+  for (int64_t first = 0; first < n_events; first += batch) {
+    L.first = (uint64_t)first;
+    L.n_events = std::min(batch, n_events - first);
+    L.accumulate = first > 0;
+    if ((e = launch_iterate(h->g, L, P, h->stream)) != hipSuccess) return e;
+  }
   if (h->timing && (e = hipEventRecord(h->events[2 * ev_slot + 1], h->stream)) != hipSuccess)
     return e;
   return launch_finalize(h->g, blocks, n_events, refine, alpha, h->stream);
@@ -491,7 +505,7 @@ int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, 
   rc = integrand_args(h, integrand_id, &P);
   if (rc) return rc;
   DeviceGuard dg(h->device);
-  const int blocks = blocks_for(h, integrand_id, n_events);
+  const int blocks = blocks_for(h, integrand_id, batch_events(h, n_events));
   if (blocks < 1) return fail(h, hipErrorInvalidValue);
   if (h->timing) VEGAS_TRY(h, ensure_events(h, 2));
   VEGAS_TRY(h, enqueue_iteration(h, integrand_id, P, n_events, seed, blocks, 0, false, 0.0));
@@ -533,7 +547,7 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
   rc = integrand_args(h, integrand_id, &P);
   if (rc) return rc;
   DeviceGuard dg(h->device);
-  const int blocks = blocks_for(h, integrand_id, n_events);
+  const int blocks = blocks_for(h, integrand_id, batch_events(h, n_events));
   if (blocks < 1) return fail(h, hipErrorInvalidValue);
   if (h->timing) VEGAS_TRY(h, ensure_events(h, 2 * (size_t)n_iter));
   auto enqueue_all = [&]() -> hipError_t {
@@ -548,7 +562,8 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
     // the iterations read and advance the iteration counter on the device, so
     // one captured sequence serves every run of the same configuration
     vegas_ctx::RunKey key{integrand_id, h->prec, n_iter, blocks, h->threads, 0,
-                          n_events, seed, alpha, h->stream, h->params[integrand_id]};
+                          n_events, h->events_limit, seed, alpha, h->stream,
+                          h->params[integrand_id]};
     if (!h->graph || !(key == h->graph_key)) {
       if (h->graph) {
         VEGAS_TRY(h, hipGraphExecDestroy(h->graph));
@@ -739,6 +754,14 @@ int vegas_set_launch(vegas_h h, int max_blocks, int threads) {
   if (threads != 64 && threads != 128 && threads != 256) return VEGAS_EINVAL;
   h->max_blocks = max_blocks;
   h->threads = threads;
+  return VEGAS_OK;
+}
+
+int vegas_set_events_limit(vegas_h h, int64_t limit) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (limit < 0) return VEGAS_EINVAL;
+  h->events_limit = limit;
   return VEGAS_OK;
 }
 

@@ -65,6 +65,7 @@ _SIGS = {
     "vegas_set_launch": ([_vp, _c.c_int, _c.c_int]),
     "vegas_timing": ([_vp, _c.c_int, _c.c_int, _pd, _c.POINTER(_i64)]),
     "vegas_set_graph": ([_vp, _c.c_int]),
+    "vegas_set_events_limit": ([_vp, _i64]),
     "vegas_server_create": ([_c.c_size_t, _c.c_int, _i64, _c.POINTER(_vp)]),
     "vegas_server_submit": ([_vp, _vp, _c.POINTER(_u64)]),
     "vegas_server_wait": ([_vp, _u64, _c.c_double, _pd, _pd, _pd, _pd]),
@@ -269,6 +270,10 @@ def vegas_dump_weights(h: Handle, integrand_id: int, seed: int, first: int, coun
 
 def vegas_set_launch(h: Handle, max_blocks: int = 0, threads: int = 0):
     _check(lib().vegas_set_launch(h, max_blocks, threads), "vegas_set_launch")
+
+
+def vegas_set_events_limit(h: Handle, limit: int):
+    _check(lib().vegas_set_events_limit(h, limit), "vegas_set_events_limit")
 
 
 def vegas_set_graph(h: Handle, enable: bool):

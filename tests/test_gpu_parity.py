@@ -304,3 +304,26 @@ def test_graph_replays_match_eager(vg):
     ms, n = vg.vegas_timing(hg, False)
     assert n == 6 and ms > 0
     assert np.all(np.abs(I_t - I_e) <= 1e-13 * np.abs(I_e))
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32_EVAL])
+def test_events_limit_batches(vg, orc, prec):
+    """An iteration split into launches of at most events_limit events (the
+    paper's batching) gives the same run; FP64 still matches the oracle."""
+    wl = W.WORKLOADS["gauss4d"]
+    ref = None
+    for limit in (0, 7_777, 33_333, 100_000):
+        h = _handle(vg, wl.dim, wl.nb, wl.fid, wl.params, prec)
+        vg.vegas_set_events_limit(h, limit)
+        I_t, s_t = vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+        I1, s1 = vg.vegas_iterate(h, wl.fid, 54_321, 3)
+        if ref is None:
+            ref = (I_t, s_t, I1)
+            continue
+        assert np.all(np.abs(I_t - ref[0]) <= 1e-13 * np.abs(ref[0])), limit
+        assert np.all(np.abs(s_t - ref[1]) <= 1e-11 * ref[1])
+        assert abs(I1 - ref[2]) <= 1e-13 * abs(ref[2])
+    if prec == W.FP64:
+        I_r, s_r, _, _ = orc.run(wl.dim, wl.nb, wl.fid, wl.params, wl.n_events, wl.seed,
+                                 wl.n_iter, wl.alpha)
+        assert np.all(np.abs(I_t - I_r) <= 1e-12 * np.abs(I_r))
