@@ -186,6 +186,19 @@ int vegas_set_hist(vegas_h h, const double *hist, size_t n);
 int vegas_get_iteration(vegas_h h, uint32_t *t);
 int vegas_set_iteration(vegas_h h, uint32_t t);
 
+/* Checkpoint and resume. The state of a handle — grid, last histogram,
+ * iteration counter, the per-iteration results behind vegas_result,
+ * integrand parameters, precision and events limit — is a flat host byte
+ * record of vegas_state_bytes bytes. vegas_save writes it into buf (host,
+ * caller-owned); vegas_load restores it into a handle of the same dim and
+ * n_bins (VEGAS_EINVAL for any other record, with the handle unchanged).
+ * Because every random number is a function of (seed, event, iteration,
+ * dimension), a run resumed from a record continues exactly as the
+ * uninterrupted run would have. */
+int vegas_state_bytes(vegas_h h, size_t *bytes);
+int vegas_save(vegas_h h, void *buf, size_t bytes);
+int vegas_load(vegas_h h, const void *buf, size_t bytes);
+
 /* Number of non-finite weights in the last iteration. */
 int vegas_nonfinite(vegas_h h, int64_t *count);
 

@@ -368,6 +368,82 @@ hipError_t collect_timing(vegas_h h, size_t n) {
 
 }  // namespace
 
+// ---- checkpoint: a flat little-endian record -------------------------------
+//   u64 magic, u32 version, i32 dim, i32 nb, i32 prec, u32 t, i32 hist_valid,
+//   i64 events_limit, u64 n_hist, then per integrand u64 np + np doubles,
+//   then n_hist I_t, n_hist sigma_t, dim*(nb+1) edges, dim*nb histogram.
+namespace {
+constexpr uint64_t kStateMagic = 0x5345544147455653ull;  // "SVEGATES"
+constexpr uint32_t kStateVersion = 1;
+
+struct Writer {
+  unsigned char* p;
+  size_t n, o = 0;
+  template <class T>
+  void put(const T& v) {
+    if (p && o + sizeof(T) <= n) std::memcpy(p + o, &v, sizeof(T));
+    o += sizeof(T);
+  }
+  void put_doubles(const double* v, size_t k) {
+    if (p && o + 8 * k <= n && k) std::memcpy(p + o, v, 8 * k);
+    o += 8 * k;
+  }
+};
+
+struct Reader {
+  const unsigned char* p;
+  size_t n, o = 0;
+  bool ok = true;
+  template <class T>
+  T get() {
+    T v{};
+    if (o + sizeof(T) > n) {
+      ok = false;
+      return v;
+    }
+    std::memcpy(&v, p + o, sizeof(T));
+    o += sizeof(T);
+    return v;
+  }
+  bool get_doubles(double* v, size_t k) {
+    if (o + 8 * k > n) return ok = false;
+    if (k) std::memcpy(v, p + o, 8 * k);
+    o += 8 * k;
+    return true;
+  }
+};
+
+// Serialise the handle's state; the grid and histogram come from the device.
+int save_state(vegas_h h, Writer& w) {
+  const size_t ne = (size_t)h->dim * (h->nb + 1), nh = (size_t)h->dim * h->nb;
+  std::vector<double> edges(ne), hist(nh);
+  if (w.p) {
+    int rc = vegas_get_grid(h, edges.data(), ne);
+    if (rc) return rc;
+    rc = vegas_get_hist(h, hist.data(), nh);
+    if (rc) return rc;
+  }
+  w.put(kStateMagic);
+  w.put(kStateVersion);
+  w.put((int32_t)h->dim);
+  w.put((int32_t)h->nb);
+  w.put((int32_t)h->prec);
+  w.put((uint32_t)h->t);
+  w.put((int32_t)(h->hist_valid ? 1 : 0));
+  w.put((int64_t)h->events_limit);
+  w.put((uint64_t)h->I_t.size());
+  for (int f = 0; f < VEGAS_N_INTEGRANDS; ++f) {
+    w.put((uint64_t)h->params[f].size());
+    w.put_doubles(h->params[f].data(), h->params[f].size());
+  }
+  w.put_doubles(h->I_t.data(), h->I_t.size());
+  w.put_doubles(h->s_t.data(), h->s_t.size());
+  w.put_doubles(edges.data(), ne);
+  w.put_doubles(hist.data(), nh);
+  return VEGAS_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* vegas_strerror(int status) { return status_name(status); }
@@ -754,6 +830,78 @@ int vegas_set_launch(vegas_h h, int max_blocks, int threads) {
   if (threads != 64 && threads != 128 && threads != 256) return VEGAS_EINVAL;
   h->max_blocks = max_blocks;
   h->threads = threads;
+  return VEGAS_OK;
+}
+
+int vegas_state_bytes(vegas_h h, size_t* bytes) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!bytes) return VEGAS_EINVAL;
+  Writer w{nullptr, 0};
+  save_state(h, w);
+  *bytes = w.o;
+  return VEGAS_OK;
+}
+
+int vegas_save(vegas_h h, void* buf, size_t bytes) {
+  int rc = ready(h);
+  if (rc) return rc;
+  size_t need = 0;
+  vegas_state_bytes(h, &need);
+  if (!buf || bytes < need) return VEGAS_EINVAL;
+  Writer w{static_cast<unsigned char*>(buf), bytes};
+  return save_state(h, w);
+}
+
+int vegas_load(vegas_h h, const void* buf, size_t bytes) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!buf) return VEGAS_EINVAL;
+  Reader r{static_cast<const unsigned char*>(buf), bytes};
+  if (r.get<uint64_t>() != kStateMagic || r.get<uint32_t>() != kStateVersion) return VEGAS_EINVAL;
+  const int dim = r.get<int32_t>(), nb = r.get<int32_t>(), prec = r.get<int32_t>();
+  const uint32_t t = r.get<uint32_t>();
+  const int hist_valid = r.get<int32_t>();
+  const int64_t limit = r.get<int64_t>();
+  const uint64_t n_hist = r.get<uint64_t>();
+  if (!r.ok || dim != h->dim || nb != h->nb || (prec != VEGAS_FP64 && prec != VEGAS_FP32_EVAL) ||
+      limit < 0 || n_hist > (uint64_t)1 << 32)
+    return VEGAS_EINVAL;
+  std::vector<double> params[VEGAS_N_INTEGRANDS];
+  for (int f = 0; f < VEGAS_N_INTEGRANDS; ++f) {
+    const uint64_t np = r.get<uint64_t>();
+    if (!r.ok || np > VEGAS_MAX_PARAMS) return VEGAS_EINVAL;
+    params[f].resize(np);
+    if (!r.get_doubles(params[f].data(), np)) return VEGAS_EINVAL;
+    if (np && build_integrand_args(f, dim, params[f].data(), (int)np, nullptr) != VEGAS_OK)
+      return VEGAS_EINVAL;
+  }
+  std::vector<double> I_t(n_hist), s_t(n_hist);
+  std::vector<double> edges((size_t)dim * (nb + 1)), hist((size_t)dim * nb);
+  if (!r.get_doubles(I_t.data(), n_hist) || !r.get_doubles(s_t.data(), n_hist) ||
+      !r.get_doubles(edges.data(), edges.size()) || !r.get_doubles(hist.data(), hist.size()))
+    return VEGAS_EINVAL;
+  // validate the arrays before touching the device, so a bad record changes nothing
+  for (int d = 0; d < dim; ++d) {
+    const double* e = edges.data() + (size_t)d * (nb + 1);
+    if (e[0] != 0.0 || e[nb] != 1.0) return VEGAS_EINVAL;
+    for (int i = 0; i < nb; ++i)
+      if (!(e[i + 1] > e[i])) return VEGAS_EINVAL;
+  }
+  for (double v : hist)
+    if (!(v >= 0.0) || !std::isfinite(v)) return VEGAS_EINVAL;
+  rc = vegas_set_grid(h, edges.data(), edges.size());
+  if (rc) return rc;
+  rc = vegas_set_hist(h, hist.data(), hist.size());
+  if (rc) return rc;
+  rc = vegas_set_iteration(h, t);
+  if (rc) return rc;
+  for (int f = 0; f < VEGAS_N_INTEGRANDS; ++f) h->params[f] = params[f];
+  h->prec = prec;
+  h->events_limit = limit;
+  h->hist_valid = hist_valid != 0;
+  h->I_t = I_t;
+  h->s_t = s_t;
   return VEGAS_OK;
 }
 

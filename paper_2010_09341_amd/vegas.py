@@ -66,6 +66,9 @@ _SIGS = {
     "vegas_timing": ([_vp, _c.c_int, _c.c_int, _pd, _c.POINTER(_i64)]),
     "vegas_set_graph": ([_vp, _c.c_int]),
     "vegas_set_events_limit": ([_vp, _i64]),
+    "vegas_state_bytes": ([_vp, _c.POINTER(_c.c_size_t)]),
+    "vegas_save": ([_vp, _vp, _c.c_size_t]),
+    "vegas_load": ([_vp, _vp, _c.c_size_t]),
     "vegas_server_create": ([_c.c_size_t, _c.c_int, _i64, _c.POINTER(_vp)]),
     "vegas_server_submit": ([_vp, _vp, _c.POINTER(_u64)]),
     "vegas_server_wait": ([_vp, _u64, _c.c_double, _pd, _pd, _pd, _pd]),
@@ -270,6 +273,24 @@ def vegas_dump_weights(h: Handle, integrand_id: int, seed: int, first: int, coun
 
 def vegas_set_launch(h: Handle, max_blocks: int = 0, threads: int = 0):
     _check(lib().vegas_set_launch(h, max_blocks, threads), "vegas_set_launch")
+
+
+def vegas_state_bytes(h: Handle) -> int:
+    n = _c.c_size_t()
+    _check(lib().vegas_state_bytes(h, _c.byref(n)), "vegas_state_bytes")
+    return n.value
+
+
+def vegas_save(h: Handle) -> bytes:
+    n = vegas_state_bytes(h)
+    buf = _c.create_string_buffer(n)
+    _check(lib().vegas_save(h, buf, n), "vegas_save")
+    return buf.raw
+
+
+def vegas_load(h: Handle, state: bytes):
+    buf = _c.create_string_buffer(bytes(state), len(state))
+    _check(lib().vegas_load(h, buf, len(state)), "vegas_load")
 
 
 def vegas_set_events_limit(h: Handle, limit: int):

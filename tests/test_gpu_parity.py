@@ -327,3 +327,30 @@ def test_events_limit_batches(vg, orc, prec):
         I_r, s_r, _, _ = orc.run(wl.dim, wl.nb, wl.fid, wl.params, wl.n_events, wl.seed,
                                  wl.n_iter, wl.alpha)
         assert np.all(np.abs(I_t - I_r) <= 1e-12 * np.abs(I_r))
+
+
+def test_checkpoint_resume(vg):
+    """A run saved after 3 of 6 iterations and resumed in a fresh handle
+    continues exactly as the uninterrupted run; a record for another shape
+    is rejected without changing the handle."""
+    wl = W.WORKLOADS["gauss4d"]
+    full = _handle(vg, wl.dim, wl.nb, wl.fid, wl.params, W.FP32_EVAL)
+    I_full, s_full = vg.vegas_run(full, wl.fid, 200_000, 9, 6, 1.5)
+    a = _handle(vg, wl.dim, wl.nb, wl.fid, wl.params, W.FP32_EVAL)
+    I_a, _ = vg.vegas_run(a, wl.fid, 200_000, 9, 3, 1.5)
+    state = vg.vegas_save(a)
+    b = vg.vegas_create(wl.dim, wl.nb)
+    vg.vegas_load(b, state)
+    assert vg.vegas_get_iteration(b) == 3
+    vg.vegas_refine(b, 1.5)
+    I_b, s_b = vg.vegas_run(b, wl.fid, 200_000, 9, 3, 1.5)
+    assert np.allclose(np.concatenate([I_a, I_b]), I_full, rtol=1e-13, atol=0)
+    I, s, _ = vg.vegas_result(b)
+    I_f, s_f, _ = vg.vegas_result(full)
+    assert abs(I - I_f) <= 1e-13 * abs(I_f)
+    other = vg.vegas_create(wl.dim + 1, wl.nb)
+    with pytest.raises(vg.VegasError):
+        vg.vegas_load(other, state)
+    with pytest.raises(vg.VegasError):
+        vg.vegas_load(b, state[:-8])
+    assert vg.vegas_get_iteration(other) == 0
