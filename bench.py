@@ -41,27 +41,36 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
     """VALU lane-instructions of one event of the Gaussian integrand: the
     minimal gfx950 instruction sequence of the method, counted operation by
     operation (issued instructions are measured separately with
-    SQ_INSTS_VALU; the difference is compiler overhead).
+    SQ_INSTS_VALU; the difference is loop and compiler overhead).
 
       Philox4x32-10 per 4 dimensions: 10 rounds x (2 v_mad_u64_u32 + 2
-        three-input xor v_bitop3) = 40 (key schedule on the scalar unit)
-      event index and loop: 64-bit add (2) + compare (1) = 3
+        three-input xor v_bitop3) = 40, less round 1's product of the
+        workgroup-uniform counter word t (scalar unit) = 39 for the first
+        block; later blocks of the same event share round 1's product of the
+        event index and the part of round 2 that does not depend on the
+        block number: 35 each
+      event index and loop: 64-bit add (1) + compare (1) = 2
       map per dimension: 32x32->64 product giving bin and remainder (1),
         fraction (FP32: alignbit + subtract; FP64: convert + fma) (2), LDS
-        address (1), x = fma (1), Jacobian multiply (1), histogram address
-        (1) = 7; FP32 also max + log2 per 4 dimensions (2)
+        histogram address (1; the grid record is read with the bin as a
+        buffer index), x = fma (1), Jacobian product (1) = 6, one product
+        fewer per 4-dimension block (FP32) or per event (FP64); FP32 also max
+        + log2 + add per 4-dimension block (3)
       Gaussian per dimension: subtract + fma = 2
-      weight: FP32 log2 split (add, fma, floor, subtract, exp2 counted as 2,
-        two converts, ldexp) = 9; FP64 exp (range reduction and degree-11
+      weight: FP32 log2 split (add, fma, floor, subtract, exp2, two
+        converts, ldexp) = 8; FP64 exp (range reduction and degree-11
         polynomial, about 22) + the Jacobian constant and product (2) = 24
-      non-finite check (class, two selects, count) = 3; moments (w^2, two
-        adds) = 3
+      non-finite check (class, two selects, count select + add) = 5;
+      moments (w^2, two adds) = 3
     """
     if fid != 2:
         return None  # counted for the Gaussian workloads only
     blocks = (dim + 3) // 4
-    n = 40 * blocks + 3 + 7 * dim + 2 * dim + 3 + 3
-    n += (2 * blocks + 9) if prec == 1 else 24
+    n = 39 + 35 * (blocks - 1) + 2 + 8 * dim + 5 + 3
+    if prec == 1:
+        n += -blocks + 3 * blocks + 8
+    else:
+        n += -1 + 24
     return n
 
 
@@ -115,6 +124,9 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the events_limit sweep, the run-time integrand and the small-workload "
+                         "latency (so a kernel trace sees only the timed launches)")
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times, so that a "
@@ -259,8 +271,13 @@ def main():
                             if slots64 else None},
         },
     }
-    out["latency_ms"]["gauss4d_fp64"] = small_latency(vg, W, args.latency_reps * 5)
-    out["events_limit_sweep"] = events_limit_sweep(vg, W, wl, max(3, args.steps // 4))
+    if not args.no_extras:
+        out["latency_ms"]["gauss4d_fp64"] = small_latency(vg, W, args.latency_reps * 5)
+        out["events_limit_sweep"] = events_limit_sweep(vg, W, wl, max(3, args.steps // 4))
+    if wl.fid == W.F_GAUSS and not args.no_extras:
+        out["user_integrand"] = user_integrand_section(
+            vg, W, wl, max(3, args.steps // 4),
+            {W.FP32_EVAL: value, W.FP64: value64})
     closed = W.gauss_closed_form(wl.dim, wl.params[0]) if wl.fid == W.F_GAUSS else None
     if closed is not None:
         out["closed_form"] = {"I": closed, "fp32_pull": (I32 - closed) / s32,
@@ -294,6 +311,54 @@ def events_limit_sweep(vg, W, wl, steps):
         rows.append({"events_limit_fraction": frac, "launches_per_iteration": int(round(1 / frac)),
                      "ms_per_run": dt * 1e3, "events_per_s": wl.n_events * wl.n_iter / dt})
     return rows
+
+
+USER_GAUSS = r"""
+// exp(-sum_d ((x_d - 1/2)/a)^2) / (a sqrt(pi))^dim, with p = {1/a^2, (a sqrt(pi))^-dim}
+__device__ double vegas_user_f64(const double* x, int dim, const double* p) {
+  double s = 0.0;
+  for (int d = 0; d < dim; ++d) {
+    const double u = x[d] - 0.5;
+    s = fma(u, u, s);
+  }
+  return exp(-p[0] * s) * p[1];
+}
+__device__ float vegas_user_f32(const float* x, int dim, const float* p) {
+  float s = 0.0f;
+  for (int d = 0; d < dim; ++d) {
+    const float u = x[d] - 0.5f;
+    s = fmaf(u, u, s);
+  }
+  return __expf(-p[0] * s) * p[1];
+}
+"""
+
+
+def user_integrand_section(vg, W, wl, steps, builtin):
+    """The workload's Gaussian written as user source in the same
+    exp-of-a-sum form as the built-in one and compiled at run time (for
+    exactly wl.dim dimensions): whole runs per second against the built-in
+    Gaussian kernel."""
+    t0 = time.perf_counter()
+    fid = vg.vegas_integrand_compile(USER_GAUSS, wl.dim)
+    compile_s = time.perf_counter() - t0
+    out = {"what": "the Gaussian as user HIP source, compiled with hiprtc",
+           "compile_s": compile_s}
+    for prec, key in ((W.FP32_EVAL, "fp32_eval"), (W.FP64, "fp64")):
+        h = vg.vegas_create(wl.dim, wl.nb)
+        a = wl.params[0]
+        vg.vegas_set_params(h, fid, [1.0 / (a * a), (a * math.sqrt(math.pi)) ** -wl.dim])
+        vg.vegas_set_precision(h, prec)
+        vg.vegas_run(h, fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            vg.vegas_reset(h)
+            I_t, s_t = vg.vegas_run(h, fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+        dt = (time.perf_counter() - t0) / steps
+        I, s, _ = vg.vegas_result(h)
+        v = wl.n_events * wl.n_iter / dt
+        out[key] = {"events_per_s": v, "vs_builtin": v / builtin[prec], "I": I, "sigma": s}
+    return out
 
 
 def small_latency(vg, W, reps):
@@ -347,12 +412,14 @@ def replay(vg, W, trace, rate, max_slots, budget=4 << 30):
     t_end = time.perf_counter()
     th.join()
     done, events, items, peak = vg.vegas_server_stats(srv)
+    ticks, graph_ticks = vg.vegas_server_ticks(srv)
     vg.vegas_server_destroy(srv)
     ev = sum(r.n_events * r.n_iter for r in trace)
     return {"rate_per_s": rate if not math.isinf(rate) else "closed-loop",
             "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3,
             "mean_ms": float(np.mean(lat)) * 1e3, "events_per_s": ev / (t_end - t0),
-            "makespan_s": t_end - t0, "peak_concurrent": peak}
+            "makespan_s": t_end - t0, "peak_concurrent": peak, "ticks": ticks,
+            "graph_replayed_ticks": graph_ticks}
 
 
 def serving_section(vg, W, n_requests):

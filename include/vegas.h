@@ -52,6 +52,7 @@ extern "C" {
 #define VEGAS_ESTATE (-4)     /* call not valid in the handle's state         */
 #define VEGAS_ENONFINITE (-5) /* some weights were not finite (results valid) */
 #define VEGAS_EBUSY (-6)      /* serving: no capacity now, try again          */
+#define VEGAS_ECOMPILE (-7)   /* run-time integrand source did not compile    */
 
 /* ---- precision modes --------------------------------------------------- */
 /* FP64: map, Jacobian, integrand and all sums in binary64.
@@ -90,11 +91,31 @@ extern "C" {
 #define VEGAS_F_BW_FLAT 5
 #define VEGAS_N_INTEGRANDS 6
 
+/* ---- integrands compiled at run time -------------------------------------
+ * Sec. 3.1 has the user supply the integrand as a function of a batch of
+ * points. vegas_integrand_compile() turns HIP C++ device source into an
+ * integrand id in [VEGAS_F_USER, VEGAS_F_USER + VEGAS_MAX_USER), usable
+ * wherever a built-in id is, except by the serving loop. The source defines
+ *   __device__ double vegas_user_f64(const double *x, int dim, const double *p);
+ *   __device__ float  vegas_user_f32(const float *x, int dim, const float *p);
+ * each returning f at the point x (dim coordinates in the unit interval) for
+ * the parameters p: those set with vegas_set_params for this id on the
+ * handle (at most VEGAS_MAX_USER_PARAMS, the rest zero; rounded to binary32
+ * for vegas_user_f32). The library multiplies by the Jacobian. FP64 mode
+ * calls vegas_user_f64, FP32_EVAL mode vegas_user_f32. HIP's device math
+ * functions (exp, log, sqrt, pow, sin, ..., their f-suffixed binary32 forms)
+ * are available without an #include; the source may not #include anything
+ * and may not define names that begin with vegas_ other than these two. */
+#define VEGAS_F_USER 64
+#define VEGAS_MAX_USER 64
+#define VEGAS_MAX_USER_PARAMS 32
+
 /* ---- limits ------------------------------------------------------------ */
 #define VEGAS_MAX_DIM 32
 #define VEGAS_MAX_BINS 512
-/* dim * n_bins may not exceed this (the grid and the histogram of one block
- * are staged in 32 bytes per (dimension, bin) of LDS, at most 64 KiB). */
+/* dim * n_bins may not exceed this (each workgroup of the iteration kernel
+ * keeps up to four copies of the w^2 histogram, 8 bytes per (dimension, bin)
+ * each, in at most 64 KiB of LDS; large grids get fewer copies). */
 #define VEGAS_MAX_CELLS 2048
 #define VEGAS_MAX_PARAMS (1 + VEGAS_MAX_DIM)
 /* vegas_run may queue at most this many iterations per call. */
@@ -188,10 +209,12 @@ int vegas_set_iteration(vegas_h h, uint32_t t);
 
 /* Checkpoint and resume. The state of a handle — grid, last histogram,
  * iteration counter, the per-iteration results behind vegas_result,
- * integrand parameters, precision and events limit — is a flat host byte
- * record of vegas_state_bytes bytes. vegas_save writes it into buf (host,
- * caller-owned); vegas_load restores it into a handle of the same dim and
- * n_bins (VEGAS_EINVAL for any other record, with the handle unchanged).
+ * parameters of the built-in integrands, precision and events limit — is a
+ * flat host byte record of vegas_state_bytes bytes (run-time integrand ids
+ * belong to the process; their parameters are not in it). vegas_save writes
+ * it into buf (host, caller-owned); vegas_load restores it into a handle of
+ * the same dim and n_bins (VEGAS_EINVAL for any other record, with the
+ * handle unchanged).
  * Because every random number is a function of (seed, event, iteration,
  * dimension), a run resumed from a record continues exactly as the
  * uninterrupted run would have. */
@@ -240,6 +263,19 @@ int vegas_timing(vegas_h h, int enable, int reset, double *iterate_ms, int64_t *
 /* Name of a status code. */
 const char *vegas_strerror(int status);
 
+/* Compile an integrand (see "integrands compiled at run time" above) for the
+ * gfx950 GPU with hiprtc. source: NUL-terminated HIP C++.
+ * dim = 0: kernels that take any dimension 1..VEGAS_MAX_DIM at run time;
+ * 1 <= dim <= VEGAS_MAX_DIM: kernels for exactly that dimension (faster; the
+ * id then serves only handles of that dimension).
+ * *integrand_id receives the new id. On VEGAS_ECOMPILE the compiler's log
+ * goes to log (at most log_bytes bytes including the NUL; log may be NULL).
+ * VEGAS_ENOMEM when VEGAS_MAX_USER ids exist. Needs no GPU: the code object
+ * is loaded onto a GPU the first time the id runs there. Ids live until the
+ * process ends. Thread-safe. */
+int vegas_integrand_compile(const char *source, int dim, int *integrand_id, char *log,
+                            size_t log_bytes);
+
 /* ---- serving: many integrals on one GPU -------------------------------- */
 /* A server keeps every admitted integral's grid, histogram and partial sums
  * resident on the device, and runs their (integral, iteration, event-chunk)
@@ -284,6 +320,18 @@ int vegas_server_iterations(vegas_server s, uint64_t ticket, double *I_t, double
  * peak concurrent integrals. Any pointer may be NULL. */
 int vegas_server_stats(vegas_server s, int64_t *completed, int64_t *events, int64_t *work_items,
                        int64_t *peak_active);
+
+/* The server advances every admitted integral by one iteration per tick.
+ * A tick whose work equals the previous tick's (the same integrals, none
+ * newly admitted, none at its last iteration) reuses the inputs already on
+ * the device; from the third such tick in a row its launches are captured
+ * once in a hipGraph and replayed until the work changes. enable = 0 launches
+ * every tick's kernels one by one (default 1). */
+int vegas_server_set_graph(vegas_server s, int enable);
+
+/* Ticks run so far and how many of them were hipGraph replays (either
+ * pointer may be NULL). */
+int vegas_server_ticks(vegas_server s, int64_t *ticks, int64_t *graph_ticks);
 
 /* Drain all queued work, then release the server. */
 int vegas_server_destroy(vegas_server s);

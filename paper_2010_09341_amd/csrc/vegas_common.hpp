@@ -7,6 +7,7 @@
 
 #include <vector>
 
+#include "vegas.h"
 #include "vegas_launch.hpp"
 #include "vegas_types.hpp"
 
@@ -26,7 +27,12 @@ DevGrid bind_grid(void* ws, int dim, int nb, int max_partials = kMaxBlocks, int 
 int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArgs* out);
 // Workgroups for the iteration kernel: enough to fill the GPU at its
 // occupancy, no more than the events need, at most cap. -1 on HIP error.
-int default_blocks(const void* kernel, int threads, size_t lds, int64_t n_events, int cap);
+int default_blocks(const IterKernel& kernel, int threads, size_t lds, int64_t n_events, int cap);
+// Whether fid names a built-in integrand or the range of run-time ones.
+inline bool integrand_id_ok(int fid) {
+  return (fid >= 0 && fid < VEGAS_N_INTEGRANDS) ||
+         (fid >= VEGAS_F_USER && fid < VEGAS_F_USER + VEGAS_MAX_USER);
+}
 // Inverse-variance combination of iteration results and chi^2 per dof.
 void combine(const std::vector<double>& I_t, const std::vector<double>& s_t, double* I,
              double* sigma, double* chi2);

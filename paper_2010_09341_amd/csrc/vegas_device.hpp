@@ -115,10 +115,16 @@ __device__ __forceinline__ double rambo24_f64(const double* x, const IntegrandAr
   return f;
 }
 
-template <int FID>
+// The integrand of a kernel compiled at run time: U::f64 / U::f32 wrap the
+// user's device functions.
+struct NoUser {};
+
+template <int FID, class U = NoUser>
 __device__ __forceinline__ double integrand_f64(const double* x, int DMAX, int D,
                                                 const IntegrandArgs& P) {
-  if constexpr (FID == kConst) {
+  if constexpr (FID == kUser) {
+    return U::f64(x, D, P.c64);
+  } else if constexpr (FID == kConst) {
     return 1.0;
   } else if constexpr (FID == kSum) {
     double s = 0.0;
@@ -218,11 +224,13 @@ __device__ __forceinline__ float rambo24_f32(const float* x, const IntegrandArgs
   return pass ? W * __builtin_amdgcn_rcpf(prod) : 0.f;
 }
 
-template <int FID>
+template <int FID, class U = NoUser>
 __device__ __forceinline__ F32Val integrand_f32(const float* x, int DMAX, int D,
                                                 const IntegrandArgs& P) {
   F32Val r{1.f, 0.f};
-  if constexpr (FID == kConst) {
+  if constexpr (FID == kUser) {
+    r.f = U::f32(x, D, P.c32);
+  } else if constexpr (FID == kConst) {
   } else if constexpr (FID == kSum) {
     float s = 0.f;
 #pragma unroll
@@ -297,7 +305,57 @@ __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem,
 // Returns w = f(x) * J in binary64 and, in hist[d], the LDS byte address of
 // the histogram entry that dimension d fell into (in this lane's copy).
 // ---------------------------------------------------------------------------
-template <int D_T, int FID, int PREC>
+// Grid records are read with structured buffer loads: one resource for the
+// whole record table (workgroup-uniform, in scalar registers) whose stride is
+// the record size, the bin as the vector index and the dimension's first
+// record as the scalar byte offset, so the address costs no vector
+// instruction. The range check (index below the table size) always passes:
+// k < nb.
+typedef uint32_t rec_u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t rec_u32x4 __attribute__((ext_vector_type(4)));
+__device__ rec_u32x2 rec_buffer_load_b64(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
+                                         int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+__device__ rec_u32x4 rec_buffer_load_b128(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
+                                          int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+
+template <class R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rec_rsrc(const void* rec,
+                                                                 uint32_t rec_bytes) {
+  // the fourth descriptor word of gfx9-family GPUs (no format conversion)
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(rec), (short)sizeof(R),
+                                           (int)rec_bytes, 0x00020000);
+}
+
+__device__ __forceinline__ Rec32 load_rec32(__amdgpu_buffer_rsrc_t r, uint32_t k,
+                                            uint32_t soff) {
+  const rec_u32x2 v = rec_buffer_load_b64(r, (int)k, 0, (int)soff, 0);
+  Rec32 g;
+  g.e = __uint_as_float(v[0]);
+  g.w = __uint_as_float(v[1]);
+  return g;
+}
+
+__device__ __forceinline__ Rec64 load_rec64(__amdgpu_buffer_rsrc_t r, uint32_t k,
+                                            uint32_t soff) {
+  const rec_u32x4 v = rec_buffer_load_b128(r, (int)k, 0, (int)soff, 0);
+  Rec64 g;
+  g.e = __hiloint2double((int)v[1], (int)v[0]);
+  g.w = __hiloint2double((int)v[3], (int)v[2]);
+  return g;
+}
+
+template <int PREC>
+struct std_conditional_rec {
+  using type = Rec32;
+};
+template <>
+struct std_conditional_rec<kFp64> {
+  using type = Rec64;
+};
+
+template <int D_T, int FID, int PREC, class U = NoUser>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
                                                int D, uint32_t nb, double nb_pow_d,
                                                float log2_nb_pow_d, const void* rec,
@@ -305,6 +363,10 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
                                                uint32_t* hist) {
   using Dm = Dims<D_T>;
   const uint32_t n_lo = (uint32_t)n, n_hi = (uint32_t)(n >> 32);
+  const uint32_t rec_bytes =
+      (uint32_t)(D_T > 0 ? D_T : D) * nb * (PREC == kFp64 ? sizeof(Rec64) : sizeof(Rec32));
+  const __amdgpu_buffer_rsrc_t rsrc =
+      make_rec_rsrc<typename std_conditional_rec<PREC>::type>(rec, rec_bytes);
   if constexpr (PREC == kFp64) {
     double x[Dm::kMax];
     double jac = 1.0;
@@ -321,17 +383,16 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const uint32_t rem = (uint32_t)prod;
             // (rem + 1/2) 2^-32, exact in binary64
             const double frac = fma((double)rem, 0x1p-32, 0x1p-33);
-            const uint32_t cell = (uint32_t)d * nb + k;
-            const Rec64 g = static_cast<const Rec64*>(rec)[cell];
+            const Rec64 g = load_rec64(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec64));
             x[d] = fma(frac, g.w, g.e);
             jac *= g.w;
-            hist[d] = hbase + (cell << 3);
+            hist[d] = hbase + (uint32_t)d * nb * 8u + (k << 3);
           }
         }
       }
     }
     // J = prod_d nb * w_d, with nb^D applied once
-    return integrand_f64<FID>(x, Dm::kMax, D_T > 0 ? D_T : D, P) * (jac * nb_pow_d);
+    return integrand_f64<FID, U>(x, Dm::kMax, D_T > 0 ? D_T : D, P) * (jac * nb_pow_d);
   } else {
     float x[Dm::kMax];
     // log2 J = sum over 4-dimension blocks of log2(prod of binary32 widths)
@@ -355,18 +416,17 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             // of a 2^-23 cell, exact in binary32
             const float frac =
                 __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u)) - 0x1.fffffep-1f;
-            const uint32_t cell = (uint32_t)d * nb + k;
-            const Rec32 g = static_cast<const Rec32*>(rec)[cell];
+            const Rec32 g = load_rec32(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec32));
             x[d] = fmaf(frac, g.w, g.e);
             wprod *= g.w;
-            hist[d] = hbase + (cell << 3);
+            hist[d] = hbase + (uint32_t)d * nb * 8u + (k << 3);
           }
         }
         l2j += __builtin_amdgcn_logf(fmaxf(wprod, 0x1p-126f));
       }
     }
     l2j += log2_nb_pow_d;  // D log2(nb)
-    const F32Val v = integrand_f32<FID>(x, Dm::kMax, D_T > 0 ? D_T : D, P);
+    const F32Val v = integrand_f32<FID, U>(x, Dm::kMax, D_T > 0 ? D_T : D, P);
     // w = f * 2^(log2 J + log2 f), the power split into a binary32 mantissa
     // in [1, 2) and an integer exponent applied in binary64.
     const float l2 = l2j + v.log2f;

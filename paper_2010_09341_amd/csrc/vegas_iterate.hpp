@@ -33,7 +33,7 @@ struct IterArgsDev {
 
 constexpr int kIterThreadsMax = 256;
 
-template <int D_T, int FID, int PREC, bool DUMP>
+template <int D_T, int FID, int PREC, bool DUMP, class U = NoUser>
 __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, IntegrandArgs P) {
   extern __shared__ __align__(16) unsigned char smem[];
   using Dm = Dims<D_T>;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
 
   if constexpr (DUMP) {
     for (; n < a.n_events; n += stride)
-      a.w_out[n] = event_weight<D_T, FID, PREC>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
+      a.w_out[n] = event_weight<D_T, FID, PREC, U>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
                                                 a.nb, a.nb_pow_d, a.log2_nb_pow_d, a.rec, hbase,
                                                 P, hist);
     return;
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
     double s1 = 0.0, s2 = 0.0;
     uint32_t bad = 0;
     for (; n < a.n_events; n += stride) {
-      double w = event_weight<D_T, FID, PREC>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
+      double w = event_weight<D_T, FID, PREC, U>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
                                               a.nb_pow_d, a.log2_nb_pow_d, a.rec, hbase, P, hist);
       if (!__builtin_isfinite(w)) {
         ++bad;

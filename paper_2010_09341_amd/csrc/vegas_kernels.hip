@@ -123,8 +123,7 @@ __global__ void k_set_t(uint32_t* t, uint32_t v) {
 // ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
-const void* iterate_kernel(int fid, int prec, int dim, bool dump) {
-  if (dim < 1 || dim > kMaxDim || (prec != kFp64 && prec != kFp32Eval)) return nullptr;
+static const void* builtin_kernel(int fid, int prec, int dim, bool dump) {
   switch (fid) {
     case kConst: return iterate_kernel_const(prec, dim, dump);
     case kSum: return iterate_kernel_sum(prec, dim, dump);
@@ -134,6 +133,23 @@ const void* iterate_kernel(int fid, int prec, int dim, bool dump) {
     case kBwFlat: return iterate_kernel_bw_flat(prec, dim, dump);
     default: return nullptr;
   }
+}
+
+IterKernel iterate_kernel(int fid, int prec, int dim, bool dump) {
+  if (dim < 1 || dim > kMaxDim || (prec != kFp64 && prec != kFp32Eval)) return IterKernel{};
+  if (fid >= kUser) return user_iterate_kernel(fid, prec, dim, dump);
+  IterKernel k;
+  k.fn = builtin_kernel(fid, prec, dim, dump);
+  return k;
+}
+
+hipError_t launch_kernel(const IterKernel& k, unsigned blocks, unsigned threads, void** args,
+                         size_t lds, hipStream_t s) {
+  if (k.fn) return hipLaunchKernel(k.fn, dim3(blocks), dim3(threads), args, lds, s);
+  if (k.mf)
+    return hipModuleLaunchKernel(k.mf, blocks, 1, 1, threads, 1, 1, (unsigned)lds, s, args,
+                                 nullptr);
+  return hipErrorInvalidValue;
 }
 
 size_t iterate_lds_bytes(int dim, int nb) { return lds_bytes(lds_layout(dim, nb)); }
@@ -160,20 +176,20 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
 
 hipError_t launch_iterate(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,
                           hipStream_t s) {
-  const void* k = iterate_kernel(L.fid, L.prec, g.dim, false);
+  const IterKernel k = iterate_kernel(L.fid, L.prec, g.dim, false);
   if (!k || L.blocks < 1 || L.blocks > g.max_blocks || L.threads < 64 ||
       L.threads > kIterThreadsMax || (L.threads & 63))
     return hipErrorInvalidValue;
   IterArgsDev a = iter_args(g, L);
   IntegrandArgs p = P;
   void* args[] = {&a, &p};
-  return hipLaunchKernel(k, dim3(L.blocks), dim3(L.threads), args,
-                         iterate_lds_bytes(g.dim, g.nb), s);
+  return launch_kernel(k, (unsigned)L.blocks, (unsigned)L.threads, args,
+                       iterate_lds_bytes(g.dim, g.nb), s);
 }
 
 hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,
                        hipStream_t s) {
-  const void* k = iterate_kernel(L.fid, L.prec, g.dim, true);
+  const IterKernel k = iterate_kernel(L.fid, L.prec, g.dim, true);
   if (!k || L.count < 1 || !L.w_out) return hipErrorInvalidValue;
   IterArgsDev a = iter_args(g, L);
   a.n_events = (uint64_t)L.count;
@@ -182,8 +198,8 @@ hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArg
   const int threads = 256;
   int64_t blocks = (L.count + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;
-  return hipLaunchKernel(k, dim3((unsigned)blocks), dim3(threads), args,
-                         iterate_lds_bytes(g.dim, g.nb), s);
+  return launch_kernel(k, (unsigned)blocks, (unsigned)threads, args,
+                       iterate_lds_bytes(g.dim, g.nb), s);
 }
 
 hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, bool refine,

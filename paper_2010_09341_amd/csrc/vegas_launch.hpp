@@ -42,9 +42,25 @@ struct IterLaunch {
   int64_t count = 0;
 };
 
+// An iteration kernel: compiled into the library (fn) or loaded from the
+// code object of a run-time integrand (mf).
+struct IterKernel {
+  const void* fn = nullptr;
+  hipFunction_t mf = nullptr;
+  explicit operator bool() const { return fn || mf; }
+  const void* key() const { return fn ? fn : (const void*)mf; }
+};
+
 // Iteration kernel (draw, map, evaluate, moments, histogram) for the given
-// integrand/precision/dimension; NULL if the combination does not exist.
-const void* iterate_kernel(int fid, int prec, int dim, bool dump);
+// integrand/precision/dimension; empty if the combination does not exist (or
+// a run-time integrand's code could not be loaded on the current GPU).
+IterKernel iterate_kernel(int fid, int prec, int dim, bool dump);
+hipError_t launch_kernel(const IterKernel& k, unsigned blocks, unsigned threads, void** args,
+                         size_t lds, hipStream_t s);
+// Run-time integrands (vegas_rtc.cpp): whether id fid exists and serves
+// `dim` dimensions, and its kernel, loaded on the current GPU on first use.
+int user_integrand_fits(int fid, int dim);
+IterKernel user_iterate_kernel(int fid, int prec, int dim, bool dump);
 size_t iterate_lds_bytes(int dim, int nb);
 
 hipError_t launch_iterate(const DevGrid& g, const IterLaunch& L, const IntegrandArgs& P,

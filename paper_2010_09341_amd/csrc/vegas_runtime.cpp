@@ -30,6 +30,7 @@ const char* status_name(int s) {
     case VEGAS_ESTATE: return "invalid state";
     case VEGAS_ENONFINITE: return "non-finite weights";
     case VEGAS_EBUSY: return "busy";
+    case VEGAS_ECOMPILE: return "integrand source did not compile";
     default: return "unknown status";
   }
 }
@@ -92,6 +93,16 @@ int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArg
   if (np < 0 || np > VEGAS_MAX_PARAMS || (np > 0 && !p)) return VEGAS_EINVAL;
   for (int i = 0; i < np; ++i)
     if (!std::isfinite(p[i])) return VEGAS_EINVAL;
+  if (fid >= VEGAS_F_USER) {
+    // run-time integrand: the parameters as given, zero-filled
+    if (!user_integrand_fits(fid, dim) || np > VEGAS_MAX_USER_PARAMS) return VEGAS_EINVAL;
+    for (int i = 0; i < np; ++i) {
+      a.c64[i] = p[i];
+      a.c32[i] = (float)p[i];
+    }
+    if (out) *out = a;
+    return VEGAS_OK;
+  }
   switch (fid) {
     case VEGAS_F_CONST:
     case VEGAS_F_SUM:
@@ -158,7 +169,7 @@ int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArg
   return VEGAS_OK;
 }
 
-int default_blocks(const void* kernel, int threads, size_t lds, int64_t n_events, int cap) {
+int default_blocks(const IterKernel& kernel, int threads, size_t lds, int64_t n_events, int cap) {
   static std::mutex mu;
   static std::map<std::pair<const void*, int>, int> cache;
   static int cus = 0;
@@ -172,12 +183,15 @@ int default_blocks(const void* kernel, int threads, size_t lds, int64_t n_events
         return -1;
       cus = prop.multiProcessorCount;
     }
-    auto key = std::make_pair(kernel, threads * 65536 + (int)(lds / 256));
+    auto key = std::make_pair(kernel.key(), threads * 65536 + (int)(lds / 256));
     auto it = cache.find(key);
     if (it == cache.end()) {
       int n = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, lds) != hipSuccess)
-        return -1;
+      const hipError_t e =
+          kernel.fn ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel.fn, threads, lds)
+                    : hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel.mf, threads,
+                                                                         lds);
+      if (e != hipSuccess) return -1;
       cache[key] = n;
       per_cu = n;
     } else {
@@ -238,6 +252,7 @@ struct vegas_ctx {
   std::vector<double> I_t, s_t;
   int64_t last_bad = 0;
   std::vector<double> params[VEGAS_N_INTEGRANDS];
+  std::map<int, std::vector<double>> user_params;  // run-time integrands
   int max_blocks = 0;
   int threads = 256;
   int64_t events_limit = 0;  // events per launch within an iteration (0: all)
@@ -297,12 +312,22 @@ int ready(vegas_h h) {
   return VEGAS_OK;
 }
 
+const std::vector<double>& params_of(vegas_h h, int fid) {
+  static const std::vector<double> none;
+  if (fid >= 0 && fid < VEGAS_N_INTEGRANDS) return h->params[fid];
+  auto it = h->user_params.find(fid);
+  return it == h->user_params.end() ? none : it->second;
+}
+
 int integrand_args(vegas_h h, int fid, IntegrandArgs* a) {
-  if (fid < 0 || fid >= VEGAS_N_INTEGRANDS) return VEGAS_EINVAL;
-  const std::vector<double>& p = h->params[fid];
+  if (!integrand_id_ok(fid)) return VEGAS_EINVAL;
+  const std::vector<double>& p = params_of(h, fid);
   int rc = build_integrand_args(fid, h->dim, p.empty() ? nullptr : p.data(), (int)p.size(), a);
   if (rc != VEGAS_OK) return rc;
-  if (!iterate_kernel(fid, h->prec, h->dim, false)) return VEGAS_EINVAL;
+  // a run-time integrand that exists for this dimension but whose code does
+  // not load on this GPU is a device error
+  if (!iterate_kernel(fid, h->prec, h->dim, false))
+    return fid >= VEGAS_F_USER ? VEGAS_EDEVICE : VEGAS_EINVAL;
   return VEGAS_OK;
 }
 
@@ -317,7 +342,7 @@ hipError_t ensure_events(vegas_h h, size_t n) {
 }
 
 int blocks_for(vegas_h h, int fid, int64_t n_events) {
-  const void* k = iterate_kernel(fid, h->prec, h->dim, false);
+  const IterKernel k = iterate_kernel(fid, h->prec, h->dim, false);
   const int cap = h->max_blocks > 0 ? std::min(h->max_blocks, kMaxBlocks) : kMaxBlocks;
   return default_blocks(k, h->threads, iterate_lds_bytes(h->dim, h->nb), n_events, cap);
 }
@@ -518,10 +543,13 @@ int vegas_reset(vegas_h h) {
 int vegas_set_params(vegas_h h, int integrand_id, const double* params, int n_params) {
   int rc = ready(h);
   if (rc) return rc;
-  if (integrand_id < 0 || integrand_id >= VEGAS_N_INTEGRANDS) return VEGAS_EINVAL;
+  if (!integrand_id_ok(integrand_id)) return VEGAS_EINVAL;
   rc = build_integrand_args(integrand_id, h->dim, params, n_params, nullptr);
   if (rc) return rc;
-  h->params[integrand_id].assign(params, params + n_params);
+  if (integrand_id >= VEGAS_F_USER)
+    h->user_params[integrand_id].assign(params, params + n_params);
+  else
+    h->params[integrand_id].assign(params, params + n_params);
   return VEGAS_OK;
 }
 
@@ -639,7 +667,7 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
     // one captured sequence serves every run of the same configuration
     vegas_ctx::RunKey key{integrand_id, h->prec, n_iter, blocks, h->threads, 0,
                           n_events, h->events_limit, seed, alpha, h->stream,
-                          h->params[integrand_id]};
+                          params_of(h, integrand_id)};
     if (!h->graph || !(key == h->graph_key)) {
       if (h->graph) {
         VEGAS_TRY(h, hipGraphExecDestroy(h->graph));

@@ -18,6 +18,7 @@
 // in one copy from pinned memory.
 #include <hip/hip_runtime_api.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -131,9 +132,23 @@ struct vegas_srv {
   int n_active = 0;
   // statistics
   int64_t completed = 0, events = 0, work_items = 0, peak_active = 0;
+  std::atomic<int64_t> ticks{0}, graph_ticks{0};
+  // A tick whose inputs equal the previous tick's (same integrals, same
+  // chunks, none new) repeats its device work without copying its inputs
+  // again. Once two ticks in a row have repeated, that work is captured in a
+  // hipGraph and replayed until the inputs change.
+  std::atomic<bool> use_graph{true};
+  std::vector<unsigned char> last_in;
+  int repeats = 0;
+  hipGraphExec_t graph = nullptr;
+  const void* graph_bufs[3] = {nullptr, nullptr, nullptr};
 
   void run();
   hipError_t tick(std::vector<Req*>& act);
+  void drop_graph() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+  }
 };
 
 hipError_t vegas_srv::tick(std::vector<Req*>& act) {
@@ -181,6 +196,65 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   for (int p = 0; p < 2; ++p)
     for (int c = 0; c < 2; ++c) o_work[p][c] = put(work[p][c].data(), work[p][c].size() * sizeof(WorkItem));
   // ---- device work ------------------------------------------------------------
+  auto fin_at = [&](size_t off) { return reinterpret_cast<const FinItem*>(in_dev.p + off); };
+  auto work_at = [&](size_t off) { return reinterpret_cast<const WorkItem*>(in_dev.p + off); };
+  // everything after the input copy: grids of new integrals, the chunks of
+  // every integral's iteration, closing the iterations, the results copy
+  auto enqueue_work = [&]() -> hipError_t {
+    hipError_t e2;
+    if ((e2 = launch_serve_init(slots_dev, fin_at(o_init), (int)init_items.size(), max_nb,
+                                stream)) != hipSuccess)
+      return e2;
+    for (int p = 0; p < 2; ++p)
+      for (int c = 0; c < 2; ++c) {
+        if (work[p][c].empty()) continue;
+        if ((e2 = launch_serve_iterate(c == 0 ? 16 : 32, p == 0 ? VEGAS_FP64 : VEGAS_FP32_EVAL,
+                                       slots_dev, work_at(o_work[p][c]),
+                                       (int)work[p][c].size(), max_lds[p][c], stream)) !=
+            hipSuccess)
+          return e2;
+      }
+    if ((e2 = launch_serve_finalize(slots_dev, fin_at(o_fin), (int)fin_items.size(), max_nb,
+                                    out_dev.p, stream)) != hipSuccess)
+      return e2;
+    return hipMemcpyAsync(out_pin.p, out_dev.p, 4 * sizeof(double) * act.size(),
+                          hipMemcpyDeviceToHost, stream);
+  };
+  ++ticks;
+  const bool same = fresh.empty() && bytes > 0 && bytes == last_in.size() &&
+                    std::memcmp(in_pin.p, last_in.data(), bytes) == 0;
+  if (same) {
+    // the device already holds these inputs (the previous tick copied them)
+    ++repeats;
+    const void* bufs[3] = {in_dev.p, out_dev.p, out_pin.p};
+    if (graph && (std::memcmp(bufs, graph_bufs, sizeof(bufs)) != 0 || !use_graph)) drop_graph();
+    if (use_graph && !graph && repeats >= 2) {
+      if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return e;
+      const hipError_t ew = enqueue_work();
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(stream, &g);
+      if (ew == hipSuccess && ec == hipSuccess) e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (ew != hipSuccess) return ew;
+      if (ec != hipSuccess) return ec;
+      if (e != hipSuccess) {
+        graph = nullptr;
+        return e;
+      }
+      std::memcpy(graph_bufs, bufs, sizeof(bufs));
+    }
+    if (graph) {
+      ++graph_ticks;
+      if ((e = hipGraphLaunch(graph, stream)) != hipSuccess) return e;
+    } else if ((e = enqueue_work()) != hipSuccess) {
+      return e;
+    }
+    return hipStreamSynchronize(stream);
+  }
+  drop_graph();
+  repeats = 0;
+  last_in.assign(in_pin.p, in_pin.p + bytes);
   for (Req* q : fresh) {
     if ((e = hipMemcpyAsync(slots_dev + q->slot, slots_pin + q->slot, sizeof(SlotDev),
                             hipMemcpyHostToDevice, stream)) != hipSuccess)
@@ -190,25 +264,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   if (bytes && (e = hipMemcpyAsync(in_dev.p, in_pin.p, bytes, hipMemcpyHostToDevice, stream)) !=
                    hipSuccess)
     return e;
-  auto fin_at = [&](size_t off) { return reinterpret_cast<const FinItem*>(in_dev.p + off); };
-  auto work_at = [&](size_t off) { return reinterpret_cast<const WorkItem*>(in_dev.p + off); };
-  if ((e = launch_serve_init(slots_dev, fin_at(o_init), (int)init_items.size(), max_nb, stream)) !=
-      hipSuccess)
-    return e;
-  for (int p = 0; p < 2; ++p)
-    for (int c = 0; c < 2; ++c) {
-      if (work[p][c].empty()) continue;
-      if ((e = launch_serve_iterate(c == 0 ? 16 : 32, p == 0 ? VEGAS_FP64 : VEGAS_FP32_EVAL,
-                                    slots_dev, work_at(o_work[p][c]), (int)work[p][c].size(),
-                                    max_lds[p][c], stream)) != hipSuccess)
-        return e;
-    }
-  if ((e = launch_serve_finalize(slots_dev, fin_at(o_fin), (int)fin_items.size(), max_nb,
-                                 out_dev.p, stream)) != hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(out_pin.p, out_dev.p, 4 * sizeof(double) * act.size(),
-                          hipMemcpyDeviceToHost, stream)) != hipSuccess)
-    return e;
+  if ((e = enqueue_work()) != hipSuccess) return e;
   return hipStreamSynchronize(stream);
 }
 
@@ -346,6 +402,8 @@ int vegas_server_submit(vegas_server s, const vegas_request* r, uint64_t* ticket
   if (!shape_ok(r->dim, r->n_bins) || r->n_events < 2 || r->n_iter < 1 ||
       r->n_iter > VEGAS_MAX_RUN_ITER || !(r->alpha >= 0.0 && r->alpha <= VEGAS_MAX_ALPHA) ||
       (r->prec != VEGAS_FP64 && r->prec != VEGAS_FP32_EVAL) || r->n_params < 0 ||
+      // the serving kernels are compiled with the built-in integrands only
+      r->integrand_id < 0 || r->integrand_id >= VEGAS_N_INTEGRANDS ||
       r->n_params > VEGAS_MAX_PARAMS || (r->n_params > 0 && !r->params))
     return VEGAS_EINVAL;
   auto q = std::make_unique<Req>();
@@ -420,6 +478,21 @@ int vegas_server_stats(vegas_server s, int64_t* completed, int64_t* events, int6
   return VEGAS_OK;
 }
 
+int vegas_server_set_graph(vegas_server s, int enable) {
+  if (!s) return VEGAS_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->use_graph = enable != 0;
+  return VEGAS_OK;
+}
+
+int vegas_server_ticks(vegas_server s, int64_t* ticks, int64_t* graph_ticks) {
+  if (!s) return VEGAS_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (ticks) *ticks = s->ticks;
+  if (graph_ticks) *graph_ticks = s->graph_ticks;
+  return VEGAS_OK;
+}
+
 int vegas_server_destroy(vegas_server s) {
   if (!s) return VEGAS_OK;
   {
@@ -430,6 +503,7 @@ int vegas_server_destroy(vegas_server s) {
   if (s->worker.joinable()) s->worker.join();
   const int rc = s->error;
   (void)hipStreamSynchronize(s->stream);
+  s->drop_graph();
   if (s->slots_pin) (void)hipHostFree(s->slots_pin);
   if (s->slots_dev) (void)hipFree(s->slots_dev);
   if (s->arena_dev) (void)hipFree(s->arena_dev);

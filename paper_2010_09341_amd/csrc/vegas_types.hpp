@@ -9,6 +9,10 @@ namespace vegas {
 
 // Integrand identifiers (the VEGAS_F_* values of the C interface).
 enum : int { kConst = 0, kSum = 1, kGauss = 2, kLoToy = 3, kRambo24 = 4, kBwFlat = 5 };
+// Integrands compiled at run time (the VEGAS_F_USER range of the C interface).
+constexpr int kUser = 64;
+constexpr int kMaxUser = 64;
+constexpr int kUserParams = 32;  // parameters of a run-time integrand (IntegrandArgs::c64/c32)
 enum : int { kFp64 = 0, kFp32Eval = 1 };
 
 constexpr int kMaxDim = 32;
@@ -20,7 +24,7 @@ constexpr int kHistCopies = 8;
 // Derived integrand constants, filled on the host from the user's parameters.
 struct IntegrandArgs {
   double d[8];
-  double c64[kMaxDim];  // Gaussian centres
+  double c64[kMaxDim];  // Gaussian centres; a run-time integrand's parameters
   float f[8];
   float c32[kMaxDim];
   int mode;

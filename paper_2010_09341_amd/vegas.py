@@ -18,18 +18,21 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvegas.so")
 
 VEGAS_OK, VEGAS_EINVAL, VEGAS_ENOMEM, VEGAS_EDEVICE = 0, -1, -2, -3
-VEGAS_ESTATE, VEGAS_ENONFINITE, VEGAS_EBUSY = -4, -5, -6
+VEGAS_ESTATE, VEGAS_ENONFINITE, VEGAS_EBUSY, VEGAS_ECOMPILE = -4, -5, -6, -7
 VEGAS_FP64, VEGAS_FP32_EVAL = 0, 1
 (VEGAS_F_CONST, VEGAS_F_SUM, VEGAS_F_GAUSS, VEGAS_F_LO_TOY, VEGAS_F_RAMBO24,
  VEGAS_F_BW_FLAT) = range(6)
 VEGAS_MAX_DIM, VEGAS_MAX_BINS, VEGAS_MAX_CELLS = 32, 512, 2048
 VEGAS_MAX_PARAMS, VEGAS_MAX_RUN_ITER = 33, 1024
+VEGAS_F_USER, VEGAS_MAX_USER, VEGAS_MAX_USER_PARAMS = 64, 64, 32
 
 
 class VegasError(RuntimeError):
-    def __init__(self, code: int, what: str):
+    def __init__(self, code: int, what: str, log: str = ""):
         self.code = code
-        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.log = log
+        msg = f"{what}: {strerror(code)} ({code})"
+        super().__init__(msg + ("\n" + log if log else ""))
 
 
 _lib = None
@@ -69,6 +72,8 @@ _SIGS = {
     "vegas_state_bytes": ([_vp, _c.POINTER(_c.c_size_t)]),
     "vegas_save": ([_vp, _vp, _c.c_size_t]),
     "vegas_load": ([_vp, _vp, _c.c_size_t]),
+    "vegas_integrand_compile": ([_c.c_char_p, _c.c_int, _c.POINTER(_c.c_int), _c.c_char_p,
+                                 _c.c_size_t]),
     "vegas_server_create": ([_c.c_size_t, _c.c_int, _i64, _c.POINTER(_vp)]),
     "vegas_server_submit": ([_vp, _vp, _c.POINTER(_u64)]),
     "vegas_server_wait": ([_vp, _u64, _c.c_double, _pd, _pd, _pd, _pd]),
@@ -76,6 +81,8 @@ _SIGS = {
     "vegas_server_stats": ([_vp, _c.POINTER(_i64), _c.POINTER(_i64), _c.POINTER(_i64),
                             _c.POINTER(_i64)]),
     "vegas_server_destroy": ([_vp]),
+    "vegas_server_set_graph": ([_vp, _c.c_int]),
+    "vegas_server_ticks": ([_vp, _c.POINTER(_i64), _c.POINTER(_i64)]),
 }
 
 
@@ -293,6 +300,18 @@ def vegas_load(h: Handle, state: bytes):
     _check(lib().vegas_load(h, buf, len(state)), "vegas_load")
 
 
+def vegas_integrand_compile(source: str, dim: int = 0) -> int:
+    """Compile HIP device source defining vegas_user_f64 / vegas_user_f32
+    into a run-time integrand id; raises VegasError carrying the compiler log
+    if it does not compile."""
+    fid = _c.c_int(-1)
+    log = _c.create_string_buffer(1 << 16)
+    rc = lib().vegas_integrand_compile(source.encode(), dim, _c.byref(fid), log, len(log))
+    if rc != VEGAS_OK:
+        raise VegasError(rc, "vegas_integrand_compile", log.value.decode(errors="replace"))
+    return fid.value
+
+
 def vegas_set_events_limit(h: Handle, limit: int):
     _check(lib().vegas_set_events_limit(h, limit), "vegas_set_events_limit")
 
@@ -376,6 +395,17 @@ def vegas_server_stats(s: Server):
     v = [_i64() for _ in range(4)]
     _check(lib().vegas_server_stats(s, *[_c.byref(x) for x in v]), "vegas_server_stats")
     return tuple(x.value for x in v)
+
+
+def vegas_server_set_graph(s: Server, enable: bool):
+    _check(lib().vegas_server_set_graph(s, int(enable)), "vegas_server_set_graph")
+
+
+def vegas_server_ticks(s: Server):
+    """(ticks, graph_ticks)."""
+    a, b = _i64(), _i64()
+    _check(lib().vegas_server_ticks(s, _c.byref(a), _c.byref(b)), "vegas_server_ticks")
+    return a.value, b.value
 
 
 def vegas_server_destroy(s: Server):

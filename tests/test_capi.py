@@ -87,3 +87,32 @@ def test_scheduler_host_logic(tmp_path):
     res = subprocess.run([exe], capture_output=True, text=True)
     assert res.returncode == 0, res.stderr
     assert res.stdout.strip() == "ok"
+
+
+def test_integrand_compile_without_gpu():
+    """Run-time integrands compile with hiprtc on a machine without a GPU:
+    consecutive ids from VEGAS_F_USER, the compiler's log on an error, and
+    argument checks."""
+    from paper_2010_09341_amd import vegas as vg
+    src = ("__device__ double vegas_user_f64(const double* x, int dim, const double* p)"
+           " { return x[0] * p[0]; }\n"
+           "__device__ float vegas_user_f32(const float* x, int dim, const float* p)"
+           " { return x[0] * p[0]; }\n")
+    a = vg.vegas_integrand_compile(src)
+    b = vg.vegas_integrand_compile(src, 3)
+    assert vg.VEGAS_F_USER <= a < vg.VEGAS_F_USER + vg.VEGAS_MAX_USER and b == a + 1
+    with pytest.raises(vg.VegasError) as e:
+        vg.vegas_integrand_compile(src.replace("x[0] * p[0]; }\n__device__ float",
+                                               "y; }\n__device__ float"))
+    assert e.value.code == vg.VEGAS_ECOMPILE
+    assert "integrand.hip:1" in e.value.log and "undeclared identifier 'y'" in e.value.log
+    with pytest.raises(vg.VegasError) as e:  # vegas_user_f32 missing
+        vg.vegas_integrand_compile(src.split("\n")[0])
+    assert e.value.code == vg.VEGAS_ECOMPILE and "vegas_user_f32" in e.value.log
+    L = vg.lib()
+    fid = ctypes.c_int(-1)
+    assert L.vegas_integrand_compile(None, 0, ctypes.byref(fid), None, 0) == -1
+    assert L.vegas_integrand_compile(src.encode(), 33, ctypes.byref(fid), None, 0) == -1
+    assert L.vegas_integrand_compile(src.encode(), -1, ctypes.byref(fid), None, 0) == -1
+    assert L.vegas_integrand_compile(src.encode(), 0, None, None, 0) == -1
+    assert fid.value == -1
