@@ -118,8 +118,8 @@ def pct(a, q):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="gauss8d")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")

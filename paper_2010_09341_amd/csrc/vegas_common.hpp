@@ -28,6 +28,12 @@ int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArg
 // Workgroups for the iteration kernel: enough to fill the GPU at its
 // occupancy, no more than the events need, at most cap. -1 on HIP error.
 int default_blocks(const IterKernel& kernel, int threads, size_t lds, int64_t n_events, int cap);
+// Threads per workgroup for the iteration kernel: of 1024, 512, 256, 128 and
+// 64, up to the largest the kernel was built for, the one that keeps the most
+// waves resident per CU (the larger on a tie). -1 on HIP error.
+int default_threads(const IterKernel& kernel, size_t lds);
+// Largest workgroup the kernel was built for; -1 on HIP error.
+int kernel_max_threads(const IterKernel& kernel);
 // Whether fid names a built-in integrand or the range of run-time ones.
 inline bool integrand_id_ok(int fid) {
   return (fid >= 0 && fid < VEGAS_N_INTEGRANDS) ||

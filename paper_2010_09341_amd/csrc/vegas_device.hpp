@@ -279,22 +279,42 @@ struct Dims {
 // Zero the workgroup's LDS histograms.
 __device__ inline void zero_hist(const LdsLayout& L, unsigned char* smem) {
   double* h = reinterpret_cast<double*>(smem);
-  const int nh = (int)(L.cstride * L.copies);
+  const int nh = (int)(L.cells * L.copies);
   for (int i = threadIdx.x; i < nh; i += blockDim.x) h[i] = 0.0;
 }
 
-// Byte address, in LDS, of this lane's histogram copy.
-__device__ inline uint32_t lane_hist_base(const LdsLayout& L) {
-  return 8u * L.cstride * (threadIdx.x & (L.copies - 1u));
+// hb[d]: LDS byte address of this lane's copy of cell (d, 0); bin k of
+// dimension d is at hb[d] + (k << L.cshift).
+// Byte offset of this lane's copy within a cell.
+__device__ inline uint32_t lane_hist_offset(const LdsLayout& L) {
+  return 8u * (threadIdx.x & (L.copies - 1u));
 }
 
-// Add the LDS histogram copies of cell i and flush non-zero sums into dst
-// (global binary64 atomics). Needs a barrier before it.
+// hb[d]: LDS byte address of this lane's copy of cell (d, 0), so that bin k
+// of dimension d is at hb[d] + (k << L.cshift) — one instruction per
+// dimension in the event loop, for KMAX registers held across it (used by
+// the kernels for an exact dimension count). The bases pass through an
+// identity DPP move, which the compiler cannot see through: otherwise it
+// folds them back into (d*nb + k) << cshift, two instructions per dimension.
+template <int KMAX>
+__device__ inline void lane_hist_bases(const LdsLayout& L, int nb, uint32_t* hb) {
+  const uint32_t lane_off = lane_hist_offset(L);
+#pragma unroll
+  for (int d = 0; d < KMAX; ++d) {
+    const uint32_t v = lane_off + (((uint32_t)d * (uint32_t)nb) << L.cshift);
+    // quad_perm(0,1,2,3): every lane reads its own value
+    hb[d] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xE4, 0xF, 0xF, false);
+  }
+}
+
+// Add the LDS histogram copies of cell i (in copy order) and flush non-zero
+// sums into dst (global binary64 atomics). Needs a barrier before it.
 __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem, double* dst) {
   const double* h = reinterpret_cast<const double*>(smem);
   for (int i = threadIdx.x; i < (int)L.cells; i += blockDim.x) {
-    double v = h[i];
-    for (uint32_t c = 1; c < L.copies; ++c) v += h[c * L.cstride + i];
+    const double* hc = h + (size_t)i * L.copies;
+    double v = hc[0];
+    for (uint32_t c = 1; c < L.copies; ++c) v += hc[c];
     if (v != 0.0) __hip_atomic_fetch_add(&dst[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -303,7 +323,9 @@ __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem,
 // One event: draw, map, evaluate. The grid records come from global memory
 // through the vector cache (a few KiB, resident after the first events).
 // Returns w = f(x) * J in binary64 and, in hist[d], the LDS byte address of
-// the histogram entry that dimension d fell into (in this lane's copy).
+// the histogram entry that dimension d fell into (in this lane's copy: from
+// hb, set by lane_hist_bases, for an exact dimension count, else from
+// lane_off).
 // ---------------------------------------------------------------------------
 // Grid records are read with structured buffer loads: one resource for the
 // whole record table (workgroup-uniform, in scalar registers) whose stride is
@@ -359,7 +381,8 @@ template <int D_T, int FID, int PREC, class U = NoUser>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
                                                int D, uint32_t nb, double nb_pow_d,
                                                float log2_nb_pow_d, const void* rec,
-                                               uint32_t hbase, const IntegrandArgs& P,
+                                               const uint32_t* hb, uint32_t lane_off,
+                                               uint32_t cshift, const IntegrandArgs& P,
                                                uint32_t* hist) {
   using Dm = Dims<D_T>;
   const uint32_t n_lo = (uint32_t)n, n_hi = (uint32_t)(n >> 32);
@@ -386,7 +409,8 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const Rec64 g = load_rec64(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec64));
             x[d] = fma(frac, g.w, g.e);
             jac *= g.w;
-            hist[d] = hbase + (uint32_t)d * nb * 8u + (k << 3);
+            hist[d] = D_T > 0 ? hb[d] + (k << cshift)
+                              : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
           }
         }
       }
@@ -419,7 +443,8 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const Rec32 g = load_rec32(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec32));
             x[d] = fmaf(frac, g.w, g.e);
             wprod *= g.w;
-            hist[d] = hbase + (uint32_t)d * nb * 8u + (k << 3);
+            hist[d] = D_T > 0 ? hb[d] + (k << cshift)
+                              : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
           }
         }
         l2j += __builtin_amdgcn_logf(fmaxf(wprod, 0x1p-126f));

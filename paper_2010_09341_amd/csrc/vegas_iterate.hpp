@@ -31,10 +31,24 @@ struct IterArgsDev {
   uint32_t nb;
 };
 
-constexpr int kIterThreadsMax = 256;
+constexpr int kIterThreadsMax = 1024;
+
+// Largest workgroup of an iteration kernel. A 1024-thread workgroup keeps 4
+// waves on every SIMD, which caps a thread at 128 VGPRs; kernels that need
+// more (binary64 RAMBO, binary64 above 12 dimensions, the run-time dimension
+// classes) are built for 256-thread workgroups instead, so that they do not
+// spill.
+template <int D_T, int FID, int PREC>
+constexpr int iter_threads_max() {
+  if (FID == kRambo24) return PREC == kFp64 ? 256 : 1024;
+  if (D_T < 0) return 256;
+  if (PREC == kFp32Eval) return 1024;
+  return D_T <= 12 ? 1024 : 256;
+}
 
 template <int D_T, int FID, int PREC, bool DUMP, class U = NoUser>
-__global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, IntegrandArgs P) {
+__global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterate(
+    IterArgsDev a, IntegrandArgs P) {
   extern __shared__ __align__(16) unsigned char smem[];
   using Dm = Dims<D_T>;
   const LdsLayout L = a.lds;
@@ -44,7 +58,9 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
   }
 
   const uint32_t t = *a.t;
-  const uint32_t hbase = lane_hist_base(L);
+  const uint32_t lane_off = lane_hist_offset(L);
+  uint32_t hb[Dm::kMax];
+  if constexpr (D_T > 0) lane_hist_bases<Dm::kMax>(L, (int)a.nb, hb);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t hist[Dm::kMax];
@@ -52,15 +68,16 @@ __global__ __launch_bounds__(kIterThreadsMax) void k_iterate(IterArgsDev a, Inte
   if constexpr (DUMP) {
     for (; n < a.n_events; n += stride)
       a.w_out[n] = event_weight<D_T, FID, PREC, U>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
-                                                a.nb, a.nb_pow_d, a.log2_nb_pow_d, a.rec, hbase,
-                                                P, hist);
+                                                a.nb, a.nb_pow_d, a.log2_nb_pow_d, a.rec, hb,
+                                                lane_off, L.cshift, P, hist);
     return;
   } else {
     double s1 = 0.0, s2 = 0.0;
     uint32_t bad = 0;
     for (; n < a.n_events; n += stride) {
       double w = event_weight<D_T, FID, PREC, U>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
-                                              a.nb_pow_d, a.log2_nb_pow_d, a.rec, hbase, P, hist);
+                                              a.nb_pow_d, a.log2_nb_pow_d, a.rec, hb, lane_off,
+                                              L.cshift, P, hist);
       if (!__builtin_isfinite(w)) {
         ++bad;
         w = 0.0;

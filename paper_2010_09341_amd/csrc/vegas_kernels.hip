@@ -152,7 +152,9 @@ hipError_t launch_kernel(const IterKernel& k, unsigned blocks, unsigned threads,
   return hipErrorInvalidValue;
 }
 
-size_t iterate_lds_bytes(int dim, int nb) { return lds_bytes(lds_layout(dim, nb)); }
+size_t iterate_lds_bytes(int dim, int nb) {
+  return lds_bytes(lds_layout(dim, nb, kIterCopies, kIterLdsBudget));
+}
 
 static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   IterArgsDev a;
@@ -170,7 +172,7 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.nb = (uint32_t)g.nb;
   a.nb_pow_d = pow((double)g.nb, (double)g.dim);
   a.log2_nb_pow_d = (float)(g.dim * log2((double)g.nb));
-  a.lds = lds_layout(g.dim, g.nb);
+  a.lds = lds_layout(g.dim, g.nb, kIterCopies, kIterLdsBudget);
   return a;
 }
 

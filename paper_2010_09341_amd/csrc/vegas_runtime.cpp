@@ -169,35 +169,84 @@ int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArg
   return VEGAS_OK;
 }
 
-int default_blocks(const IterKernel& kernel, int threads, size_t lds, int64_t n_events, int cap) {
-  static std::mutex mu;
-  static std::map<std::pair<const void*, int>, int> cache;
-  static int cus = 0;
-  int per_cu = 0;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    if (cus == 0) {
-      int dev = 0;
-      hipDeviceProp_t prop;
-      if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return -1;
-      cus = prop.multiProcessorCount;
-    }
-    auto key = std::make_pair(kernel.key(), threads * 65536 + (int)(lds / 256));
-    auto it = cache.find(key);
-    if (it == cache.end()) {
-      int n = 0;
-      const hipError_t e =
-          kernel.fn ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel.fn, threads, lds)
-                    : hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel.mf, threads,
-                                                                         lds);
-      if (e != hipSuccess) return -1;
-      cache[key] = n;
-      per_cu = n;
-    } else {
-      per_cu = it->second;
+namespace {
+
+std::mutex g_occ_mu;
+int g_cus = 0;
+std::map<std::pair<const void*, int>, int> g_occ;  // (kernel, threads and LDS) -> blocks per CU
+
+// Resident workgroups per CU of `kernel` (-1 on a HIP error). Holds g_occ_mu.
+int blocks_per_cu_locked(const IterKernel& kernel, int threads, size_t lds) {
+  if (g_cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+      return -1;
+    g_cus = prop.multiProcessorCount;
+  }
+  const auto key = std::make_pair(kernel.key(), threads * 65536 + (int)(lds / 256));
+  auto it = g_occ.find(key);
+  if (it != g_occ.end()) return it->second;
+  int n = 0;
+  const hipError_t e =
+      kernel.fn ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel.fn, threads, lds)
+                : hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel.mf, threads, lds);
+  if (e != hipSuccess) return -1;
+  g_occ[key] = n;
+  return n;
+}
+
+std::map<const void*, int> g_max_threads;  // kernel -> largest workgroup it was built for
+
+int max_threads_locked(const IterKernel& kernel) {
+  auto it = g_max_threads.find(kernel.key());
+  if (it != g_max_threads.end()) return it->second;
+  int n = 0;
+  if (kernel.fn) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, kernel.fn) != hipSuccess) return -1;
+    n = a.maxThreadsPerBlock;
+  } else if (hipFuncGetAttribute(&n, HIP_FUNC_ATTRIBUTE_MAX_THREADS_PER_BLOCK, kernel.mf) !=
+             hipSuccess) {
+    return -1;
+  }
+  g_max_threads[kernel.key()] = n;
+  return n;
+}
+
+}  // namespace
+
+int kernel_max_threads(const IterKernel& kernel) {
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  return max_threads_locked(kernel);
+}
+
+int default_threads(const IterKernel& kernel, size_t lds) {
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  const int max_threads = max_threads_locked(kernel);
+  if (max_threads < 0) return -1;
+  int best = 0, best_waves = -1;
+  for (int threads : {1024, 512, 256, 128, 64}) {
+    if (threads > max_threads) continue;
+    const int n = blocks_per_cu_locked(kernel, threads, lds);
+    if (n < 0) return -1;
+    const int waves = n * threads / 64;
+    if (waves > best_waves) {
+      best = threads;
+      best_waves = waves;
     }
   }
+  return best;
+}
+
+int default_blocks(const IterKernel& kernel, int threads, size_t lds, int64_t n_events, int cap) {
+  int per_cu = 0, cus = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    per_cu = blocks_per_cu_locked(kernel, threads, lds);
+    cus = g_cus;
+  }
+  if (per_cu < 0) return -1;
   int64_t want = (n_events + threads - 1) / threads;
   int64_t fill = (int64_t)std::max(per_cu, 1) * cus;
   int64_t b = std::min<int64_t>(want, fill);
@@ -254,7 +303,7 @@ struct vegas_ctx {
   std::vector<double> params[VEGAS_N_INTEGRANDS];
   std::map<int, std::vector<double>> user_params;  // run-time integrands
   int max_blocks = 0;
-  int threads = 256;
+  int threads = 0;  // 0: chosen per kernel (default_threads)
   int64_t events_limit = 0;  // events per launch within an iteration (0: all)
   bool timing = false;
   double time_ms = 0.0;
@@ -341,10 +390,30 @@ hipError_t ensure_events(vegas_h h, size_t n) {
   return hipSuccess;
 }
 
-int blocks_for(vegas_h h, int fid, int64_t n_events) {
+// Launch shape of the iteration kernel for n_events per launch: the handle's
+// thread count (0: the one that keeps the most waves resident) and enough
+// workgroups to fill the GPU. VEGAS_EINVAL if the handle's thread count
+// exceeds the workgroup the kernel was built for; VEGAS_EDEVICE on a HIP
+// error.
+struct Shape {
+  int blocks = 0, threads = 0;
+};
+
+int shape_for(vegas_h h, int fid, int64_t n_events, Shape* s) {
   const IterKernel k = iterate_kernel(fid, h->prec, h->dim, false);
+  const size_t lds = iterate_lds_bytes(h->dim, h->nb);
+  if (h->threads > 0) {
+    const int max_threads = kernel_max_threads(k);
+    if (max_threads < 0) return VEGAS_EDEVICE;
+    if (h->threads > max_threads) return VEGAS_EINVAL;
+    s->threads = h->threads;
+  } else {
+    s->threads = default_threads(k, lds);
+    if (s->threads < 1) return VEGAS_EDEVICE;
+  }
   const int cap = h->max_blocks > 0 ? std::min(h->max_blocks, kMaxBlocks) : kMaxBlocks;
-  return default_blocks(k, h->threads, iterate_lds_bytes(h->dim, h->nb), n_events, cap);
+  s->blocks = default_blocks(k, s->threads, lds, n_events, cap);
+  return s->blocks < 1 ? VEGAS_EDEVICE : VEGAS_OK;
 }
 
 // Events per launch of the iteration kernel.
@@ -357,15 +426,15 @@ int64_t batch_events(vegas_h h, int64_t n_events) {
 // limit the iteration's events go through several launches of at most that
 // many events, each adding to the workgroup partials of the previous ones.
 hipError_t enqueue_iteration(vegas_h h, int fid, const IntegrandArgs& P, int64_t n_events,
-                             uint64_t seed, int blocks, size_t ev_slot, bool refine,
+                             uint64_t seed, const Shape& shape, size_t ev_slot, bool refine,
                              double alpha) {
   const int64_t batch = batch_events(h, n_events);
   IterLaunch L;
   L.fid = fid;
   L.prec = h->prec;
   L.seed = seed;
-  L.blocks = blocks;
-  L.threads = h->threads;
+  L.blocks = shape.blocks;
+  L.threads = shape.threads;
   hipError_t e;
   if (h->timing && (e = hipEventRecord(h->events[2 * ev_slot], h->stream)) != hipSuccess) return e;
   for (int64_t first = 0; first < n_events; first += batch) {
@@ -376,7 +445,7 @@ hipError_t enqueue_iteration(vegas_h h, int fid, const IntegrandArgs& P, int64_t
   }
   if (h->timing && (e = hipEventRecord(h->events[2 * ev_slot + 1], h->stream)) != hipSuccess)
     return e;
-  return launch_finalize(h->g, blocks, n_events, refine, alpha, h->stream);
+  return launch_finalize(h->g, shape.blocks, n_events, refine, alpha, h->stream);
 }
 
 hipError_t collect_timing(vegas_h h, size_t n) {
@@ -609,10 +678,12 @@ int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, 
   rc = integrand_args(h, integrand_id, &P);
   if (rc) return rc;
   DeviceGuard dg(h->device);
-  const int blocks = blocks_for(h, integrand_id, batch_events(h, n_events));
-  if (blocks < 1) return fail(h, hipErrorInvalidValue);
+  Shape shape;
+  rc = shape_for(h, integrand_id, batch_events(h, n_events), &shape);
+  if (rc == VEGAS_EDEVICE) return fail(h, hipErrorInvalidValue);
+  if (rc) return rc;
   if (h->timing) VEGAS_TRY(h, ensure_events(h, 2));
-  VEGAS_TRY(h, enqueue_iteration(h, integrand_id, P, n_events, seed, blocks, 0, false, 0.0));
+  VEGAS_TRY(h, enqueue_iteration(h, integrand_id, P, n_events, seed, shape, 0, false, 0.0));
   const size_t slot = h->t % kRing;
   VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.results + 4 * slot, 4 * sizeof(double),
                               hipMemcpyDeviceToHost, h->stream));
@@ -651,12 +722,14 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
   rc = integrand_args(h, integrand_id, &P);
   if (rc) return rc;
   DeviceGuard dg(h->device);
-  const int blocks = blocks_for(h, integrand_id, batch_events(h, n_events));
-  if (blocks < 1) return fail(h, hipErrorInvalidValue);
+  Shape shape;
+  rc = shape_for(h, integrand_id, batch_events(h, n_events), &shape);
+  if (rc == VEGAS_EDEVICE) return fail(h, hipErrorInvalidValue);
+  if (rc) return rc;
   if (h->timing) VEGAS_TRY(h, ensure_events(h, 2 * (size_t)n_iter));
   auto enqueue_all = [&]() -> hipError_t {
     for (int i = 0; i < n_iter; ++i) {
-      hipError_t e = enqueue_iteration(h, integrand_id, P, n_events, seed, blocks, i,
+      hipError_t e = enqueue_iteration(h, integrand_id, P, n_events, seed, shape, i,
                                        i + 1 < n_iter, alpha);
       if (e != hipSuccess) return e;
     }
@@ -665,7 +738,7 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
   if (h->use_graph && !h->timing) {
     // the iterations read and advance the iteration counter on the device, so
     // one captured sequence serves every run of the same configuration
-    vegas_ctx::RunKey key{integrand_id, h->prec, n_iter, blocks, h->threads, 0,
+    vegas_ctx::RunKey key{integrand_id, h->prec, n_iter, shape.blocks, shape.threads, 0,
                           n_events, h->events_limit, seed, alpha, h->stream,
                           params_of(h, integrand_id)};
     if (!h->graph || !(key == h->graph_key)) {
@@ -854,8 +927,9 @@ int vegas_set_launch(vegas_h h, int max_blocks, int threads) {
   int rc = ready(h);
   if (rc) return rc;
   if (max_blocks < 0 || max_blocks > kMaxBlocks) return VEGAS_EINVAL;
-  if (threads == 0) threads = 256;
-  if (threads != 64 && threads != 128 && threads != 256) return VEGAS_EINVAL;
+  if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
+      threads != 1024)
+    return VEGAS_EINVAL;
   h->max_blocks = max_blocks;
   h->threads = threads;
   return VEGAS_OK;

@@ -23,12 +23,12 @@ namespace vegas {
 template <int D_T, int FID, int PREC>
 __device__ void serve_chunk(const SlotDev& S, uint32_t chunk, unsigned char* smem) {
   using Dm = Dims<D_T>;
-  const LdsLayout L = lds_layout(S.dim, (int)S.nb);
+  const LdsLayout L = lds_layout(S.dim, (int)S.nb, kServeCopies, kServeLdsBudget);
   zero_hist(L, smem);
   __syncthreads();
   const void* rec = PREC == kFp64 ? (const void*)S.rec64 : (const void*)S.rec32;
   const uint32_t t = *S.t;
-  const uint32_t hbase = lane_hist_base(L);
+  const uint32_t lane_off = lane_hist_offset(L);
   const uint64_t begin = (uint64_t)chunk * S.chunk_events;
   uint64_t end = begin + S.chunk_events;
   if (end > S.n_events) end = S.n_events;
@@ -37,7 +37,8 @@ __device__ void serve_chunk(const SlotDev& S, uint32_t chunk, unsigned char* sme
   uint32_t hist[Dm::kMax];
   for (uint64_t n = begin + threadIdx.x; n < end; n += blockDim.x) {
     double w = event_weight<D_T, FID, PREC>(n, t, S.seed_lo, S.seed_hi, S.dim, S.nb, S.nb_pow_d,
-                                            S.log2_nb_pow_d, rec, hbase, S.P, hist);
+                                            S.log2_nb_pow_d, rec, nullptr, lane_off, L.cshift, S.P,
+                                            hist);
     if (!__builtin_isfinite(w)) {
       ++bad;
       w = 0.0;

@@ -169,7 +169,8 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
     const int pc = q->r.prec == VEGAS_FP64 ? 0 : 1;
     const int dc = dim <= 16 ? 0 : 1;
     for (uint32_t c = 0; c < q->n_chunks; ++c) work[pc][dc].push_back(WorkItem{(uint32_t)q->slot, c});
-    max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(lds_layout(dim, nb)));
+    const LdsLayout L = lds_layout(dim, nb, kServeCopies, kServeLdsBudget);
+    max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(L));
     const uint32_t refine = q->iters + 1 < q->r.n_iter ? 1u : 0u;
     fin_items.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
     for (int d = 0; d < dim; ++d) fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine});

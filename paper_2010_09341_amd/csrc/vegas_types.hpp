@@ -44,27 +44,39 @@ struct alignas(8) Rec32 {
 };
 
 // LDS of the iteration kernels' workgroups: `copies` histograms of w^2
-// (binary64) for the cells (d, k) = d * nb + k, copy stride cstride entries;
-// lane l adds into copy l % copies, which splits the lanes of a wave that hit
-// the same bin. The grid records are read through the vector cache, so every
-// LDS access is a binary64 atomic at an 8-byte stride. At most 64 KiB.
+// (binary64), interleaved per cell: the entry of cell (d, k) = d * nb + k in
+// copy c is at index cell * copies + c, and lane l adds into copy
+// l % copies. With 16 copies the 16 lanes that the LDS serves together hit 16
+// distinct bank pairs whatever their bins, so the atomics never conflict
+// (fewer copies for the largest grids, within the kernel's LDS budget; one
+// copy of the largest grid, 2048 cells, takes 16 KiB).
 struct LdsLayout {
   uint32_t cells;
-  uint32_t cstride;  // histogram copy stride in entries
-  uint32_t copies;   // 1, 2 or 4
+  uint32_t copies;  // 1, 2, 4, 8 or 16
+  uint32_t cshift;  // log2(8 * copies): bytes per cell as a shift
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int dim, int nb) {
+// Copies and LDS budget of the single-integral iteration kernel (up to two
+// 1024-thread workgroups per CU) and of the serving kernel (256-thread
+// workgroups, four or more per CU; smaller chunks flush more often).
+constexpr uint32_t kIterCopies = 16;
+constexpr uint32_t kIterLdsBudget = 65536;
+constexpr uint32_t kServeCopies = 8;
+constexpr uint32_t kServeLdsBudget = 32768;
+
+__host__ __device__ inline LdsLayout lds_layout(int dim, int nb, uint32_t max_copies,
+                                                uint32_t budget) {
   LdsLayout L;
   L.cells = (uint32_t)(dim * nb);
-  L.cstride = L.cells + 4u;
-  L.copies = 4u;
-  while (L.copies > 1u && 8u * L.cstride * L.copies > 65536u) L.copies >>= 1;
+  L.copies = max_copies;
+  while (L.copies > 1u && 8u * L.cells * L.copies > budget) L.copies >>= 1;
+  L.cshift = 3u;
+  while ((1u << (L.cshift - 3u)) < L.copies) ++L.cshift;
   return L;
 }
 
 __host__ __device__ inline uint32_t lds_bytes(const LdsLayout& L) {
-  return 8u * L.cstride * L.copies;
+  return 8u * L.cells * L.copies;
 }
 
 // Workgroup partial slots and result-ring entries per integral.

@@ -94,6 +94,11 @@ def lib():
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"{LIB_PATH} is missing: build it with "
                                   "`python -m paper_2010_09341_amd.build`")
+            # torch ships its own HIP runtime under the same shared-object
+            # name as the system one; loading torch first makes the library
+            # bind to that runtime, so that both share one (loading the
+            # library first has left torch without a usable GPU)
+            import torch  # noqa: F401
             L = ctypes.CDLL(LIB_PATH)
             for name, args in _SIGS.items():
                 try:

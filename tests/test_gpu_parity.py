@@ -232,13 +232,31 @@ def test_launch_shape_independence(vg):
     same shape gives bitwise the same estimate."""
     grid = W.random_grid(np.random.default_rng(3), 7, 33)
     res = []
-    for blocks, threads in ((0, 0), (0, 0), (7, 64), (1, 256), (300, 128)):
+    for blocks, threads in ((0, 0), (0, 0), (7, 64), (1, 256), (300, 128), (0, 512), (3, 1024)):
         h = _handle(vg, 7, 33, W.F_SUM, None, W.FP64, grid)
         vg.vegas_set_launch(h, blocks, threads)
         res.append(vg.vegas_iterate(h, W.F_SUM, 123_457, 9))
     assert res[0] == res[1]
     for I, s in res[2:]:
         assert _close(I, res[0][0], rtol=1e-14)
+
+
+def test_workgroup_bound_of_heavy_kernels(vg, orc):
+    """Kernels that need more than 128 registers per thread (binary64 above
+    12 dimensions) are built for 256-thread workgroups: asking for 1024
+    threads is rejected before any device work, and the handle still runs
+    (and matches the oracle) with the default shape."""
+    grid = W.random_grid(np.random.default_rng(4), 14, 20)
+    h = _handle(vg, 14, 20, W.F_GAUSS, [0.3], W.FP64, grid, 2)
+    vg.vegas_set_launch(h, 0, 1024)
+    with pytest.raises(vg.VegasError) as e:
+        vg.vegas_iterate(h, W.F_GAUSS, 50_000, 1)
+    assert e.value.code == vg.VEGAS_EINVAL
+    assert vg.vegas_get_iteration(h) == 2
+    vg.vegas_set_launch(h, 0, 0)
+    I, s = vg.vegas_iterate(h, W.F_GAUSS, 50_000, 1)
+    I_r, s_r, _, _ = orc.iterate(grid, W.F_GAUSS, [0.3], 50_000, 1, 2)
+    assert _close(I, I_r) and _close(s, s_r, rtol=1e-10)
 
 
 def test_own_memory_matches_torch_memory(vg):
