@@ -33,9 +33,11 @@ __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, R
 }
 
 // (I, sigma, non-finite count, t) of the iteration into results[t % ring]
-// (and into out[0..3] if out is not null), then t += 1.
+// (and into mirror[t % ring] and out[0..3] where those are not null), then
+// t += 1.
 __device__ inline void wg_moments(const double* partials, int n_partials, double N, uint32_t* t,
-                                  double* results, int ring, double* out) {
+                                  double* results, int ring, double* out,
+                                  double* mirror = nullptr) {
   const uint32_t tt = *t;  // issued together with the partial loads
   // The partials were written by workgroups on every XCD, so each load goes
   // to memory: issue 8 independent 32-byte loads per lane before adding.
@@ -72,6 +74,13 @@ __device__ inline void wg_moments(const double* partials, int n_partials, double
       out[1] = sig;
       out[2] = b;
       out[3] = (double)tt;
+    }
+    if (mirror) {
+      double* m = mirror + 4 * (size_t)(tt % (uint32_t)ring);
+      m[0] = I;
+      m[1] = sig;
+      m[2] = b;
+      m[3] = (double)tt;
     }
     *t = tt + 1;
   }

@@ -35,6 +35,7 @@ struct FinArgs {
   uint32_t* t;
   const double* partials;
   double* results;
+  double* results_host;
   double* copies;
   double* hist;
   double* edges;
@@ -52,7 +53,8 @@ struct FinArgs {
 __global__ __launch_bounds__(64) void k_finalize(FinArgs a) {
   extern __shared__ __align__(16) double fsm[];
   if (blockIdx.x == 0) {
-    wg_moments(a.partials, a.blocks, a.n_events, a.t, a.results, a.ring, nullptr);
+    wg_moments(a.partials, a.blocks, a.n_events, a.t, a.results, a.ring, nullptr,
+               a.results_host);
     return;
   }
   const int d = blockIdx.x - 1;
@@ -211,6 +213,7 @@ hipError_t launch_finalize(const DevGrid& g, int blocks, int64_t n_events, bool 
   a.t = g.t;
   a.partials = g.partials;
   a.results = g.results;
+  a.results_host = g.results_host;
   a.copies = g.copies;
   a.hist = g.hist;
   a.edges = g.edges;

@@ -22,6 +22,9 @@ struct DevGrid {
   void* rec32 = nullptr;       // [dim][nb] Rec32
   double* partials = nullptr;  // [max_blocks][4]: sum w, sum w^2, non-finite count, 0
   double* results = nullptr;   // [ring][4]: I, sigma, non-finite count, t
+  // optional host-mapped mirror of results (pinned host memory, written by
+  // the finalize kernel so that no copy is needed to read a result)
+  double* results_host = nullptr;
   int max_blocks = 0;
   int ring = 0;
 };

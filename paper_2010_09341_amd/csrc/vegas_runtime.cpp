@@ -295,6 +295,8 @@ struct vegas_ctx {
   DevGrid g;
   double* pinned = nullptr;
   size_t pinned_n = 0;
+  double* ring_host = nullptr;  // [kRing][4] host mirror of the result ring
+  double* ring_dev = nullptr;   // the same memory as the device addresses it
   uint32_t t = 0;
   bool hist_valid = false;
   bool poisoned = false;
@@ -383,7 +385,10 @@ int integrand_args(vegas_h h, int fid, IntegrandArgs* a) {
 hipError_t ensure_events(vegas_h h, size_t n) {
   while (h->events.size() < n) {
     hipEvent_t e;
-    hipError_t rc = hipEventCreate(&e);
+    // timing only (read after the stream is synchronised): no system-scope
+    // fence, so recording the event does not write back and invalidate the
+    // caches around the kernel it brackets
+    hipError_t rc = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     if (rc != hipSuccess) return rc;
     h->events.push_back(e);
   }
@@ -566,10 +571,18 @@ int vegas_create(int dim, int n_bins, vegas_h* out) {
   if (e == hipSuccess) {
     h->ws = h->own_ws;
     h->g = bind_grid(h->ws, dim, n_bins);
-    h->pinned_n = std::max<size_t>(4 * kRing, (size_t)dim * (n_bins + 1));
+    h->pinned_n = (size_t)dim * (n_bins + 1);
     e = hipHostMalloc(reinterpret_cast<void**>(&h->pinned), sizeof(double) * h->pinned_n,
                       hipHostMallocDefault);
   }
+  // the result ring's host mirror: pinned, mapped into the device's address
+  // space, coherent (the finalize kernel's stores reach host memory)
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&h->ring_host), sizeof(double) * 4 * kRing,
+                      hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess)
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&h->ring_dev), h->ring_host, 0);
+  if (e == hipSuccess) h->g.results_host = h->ring_dev;
   if (e == hipSuccess) e = launch_init_grid(h->g, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
@@ -590,6 +603,7 @@ int vegas_destroy(vegas_h h) {
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->own_ws) (void)hipFree(h->own_ws);
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->ring_host) (void)hipHostFree(h->ring_host);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   delete h;
   return VEGAS_OK;
@@ -660,7 +674,13 @@ int vegas_bind_workspace(vegas_h h, void* dev_ptr, size_t bytes) {
     VEGAS_TRY(h, hipStreamSynchronize(h->stream));
     h->ws = next;
     h->g = bind_grid(h->ws, h->dim, h->nb);
-    // records hold no pointers, the copy preserved everything
+    h->g.results_host = h->ring_dev;
+    // records hold no pointers, the copy preserved everything; a captured
+    // run refers to the old workspace
+    if (h->graph) {
+      VEGAS_TRY(h, hipGraphExecDestroy(h->graph));
+      h->graph = nullptr;
+    }
   }
   if (dev_ptr && h->own_ws) {
     VEGAS_TRY(h, hipFree(h->own_ws));
@@ -684,14 +704,13 @@ int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, 
   if (rc) return rc;
   if (h->timing) VEGAS_TRY(h, ensure_events(h, 2));
   VEGAS_TRY(h, enqueue_iteration(h, integrand_id, P, n_events, seed, shape, 0, false, 0.0));
-  const size_t slot = h->t % kRing;
-  VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.results + 4 * slot, 4 * sizeof(double),
-                              hipMemcpyDeviceToHost, h->stream));
+  // finalize writes the result into the host-mapped ring as well
   VEGAS_TRY(h, hipStreamSynchronize(h->stream));
   VEGAS_TRY(h, collect_timing(h, 1));
-  *I = h->pinned[0];
-  *sigma = h->pinned[1];
-  h->last_bad = (int64_t)h->pinned[2];
+  const double* r = h->ring_host + 4 * (h->t % kRing);
+  *I = r[0];
+  *sigma = r[1];
+  h->last_bad = (int64_t)r[2];
   h->t += 1;
   h->hist_valid = true;
   h->I_t.push_back(*I);
@@ -766,21 +785,12 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
   } else {
     VEGAS_TRY(h, enqueue_all());
   }
-  // copy back only this run's result entries (at most two pieces of the ring)
-  {
-    const size_t first = h->t % kRing;
-    const size_t n1 = std::min<size_t>((size_t)n_iter, kRing - first);
-    VEGAS_TRY(h, hipMemcpyAsync(h->pinned + 4 * first, h->g.results + 4 * first,
-                                4 * sizeof(double) * n1, hipMemcpyDeviceToHost, h->stream));
-    if (n1 < (size_t)n_iter)
-      VEGAS_TRY(h, hipMemcpyAsync(h->pinned, h->g.results, 4 * sizeof(double) * (n_iter - n1),
-                                  hipMemcpyDeviceToHost, h->stream));
-  }
+  // each finalize wrote its result into the host-mapped ring as well
   VEGAS_TRY(h, hipStreamSynchronize(h->stream));
   VEGAS_TRY(h, collect_timing(h, (size_t)n_iter));
   int64_t bad = 0;
   for (int i = 0; i < n_iter; ++i) {
-    const double* r = h->pinned + 4 * ((h->t + i) % kRing);
+    const double* r = h->ring_host + 4 * ((h->t + i) % kRing);
     if (I_t) I_t[i] = r[0];
     if (sigma_t) sigma_t[i] = r[1];
     h->I_t.push_back(r[0]);
