@@ -404,8 +404,10 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const uint64_t prod = (uint64_t)r.v[i] * nb;
             const uint32_t k = (uint32_t)(prod >> 32);
             const uint32_t rem = (uint32_t)prod;
-            // (rem + 1/2) 2^-32, exact in binary64
-            const double frac = fma((double)rem, 0x1p-32, 0x1p-33);
+            // (rem + 1/2) 2^-32, exact in binary64 (an add with an inline
+            // constant and a product by a scalar register: as one fma the
+            // two constants cost two register moves per dimension)
+            const double frac = ((double)rem + 0.5) * 0x1p-32;
             const Rec64 g = load_rec64(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec64));
             x[d] = fma(frac, g.w, g.e);
             jac *= g.w;

@@ -8,7 +8,10 @@
 //   1. newly admitted integrals get their uniform grid (k_serve_init);
 //   2. one launch per (precision, dimension class) runs every event chunk of
 //      every admitted integral's current iteration (k_serve_iterate), so
-//      small and large integrals share the GPU;
+//      small integrals share the GPU; an integral of at least 2^20 events
+//      per iteration instead gets one launch of the single-integral
+//      iteration kernel (exact dimension count, up to 1024-thread
+//      workgroups), whose workgroups take the place of its chunks;
 //   3. one launch closes all those iterations: moments, histogram reduction
 //      and refinement (k_serve_finalize);
 //   4. the per-integral (I_t, sigma_t) come back in one 32-byte-per-integral
@@ -47,6 +50,11 @@ struct Req {
   IntegrandArgs P{};
   int64_t chunk = 0;
   uint32_t n_chunks = 0;
+  // A large request runs each iteration as one launch of the single-integral
+  // iteration kernel (its workgroups take the place of chunks).
+  bool big = false;
+  int big_threads = 0;
+  DevGrid g{};
   Layout L{};
   int slot = -1;
   size_t off = 0;
@@ -58,6 +66,21 @@ struct Req {
   bool done = false;
   int status = VEGAS_OK;
   double I = 0, sigma = 0, chi2 = 0;
+};
+
+// Requests of at least this many events per iteration run as single-integral
+// iteration-kernel launches rather than as chunks of the batched kernel.
+constexpr int64_t kServeBigEvents = int64_t(1) << 20;
+
+struct DeviceGuardSrv {
+  int prev = -1;
+  explicit DeviceGuardSrv(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess || prev == dev || hipSetDevice(dev) != hipSuccess)
+      prev = -1;
+  }
+  ~DeviceGuardSrv() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
 };
 
 Layout slot_layout(int dim, int nb, uint32_t n_chunks, int ring) {
@@ -157,7 +180,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   std::vector<WorkItem> work[2][2];  // [prec][dim class 16 / 32]
   int max_lds[2][2] = {{0, 0}, {0, 0}};
   int max_nb = 2;
-  std::vector<Req*> fresh;
+  std::vector<Req*> fresh, big;
   for (size_t i = 0; i < act.size(); ++i) {
     Req* q = act[i];
     const int dim = q->r.dim, nb = q->r.n_bins;
@@ -166,11 +189,16 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
       fresh.push_back(q);
       for (int d = 0; d < dim; ++d) init_items.push_back(FinItem{(uint32_t)q->slot, d, 0, 0});
     }
-    const int pc = q->r.prec == VEGAS_FP64 ? 0 : 1;
-    const int dc = dim <= 16 ? 0 : 1;
-    for (uint32_t c = 0; c < q->n_chunks; ++c) work[pc][dc].push_back(WorkItem{(uint32_t)q->slot, c});
-    const LdsLayout L = lds_layout(dim, nb, kServeCopies, kServeLdsBudget);
-    max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(L));
+    if (q->big) {
+      big.push_back(q);
+    } else {
+      const int pc = q->r.prec == VEGAS_FP64 ? 0 : 1;
+      const int dc = dim <= 16 ? 0 : 1;
+      for (uint32_t c = 0; c < q->n_chunks; ++c)
+        work[pc][dc].push_back(WorkItem{(uint32_t)q->slot, c});
+      const LdsLayout L = lds_layout(dim, nb, kServeCopies, kServeLdsBudget);
+      max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(L));
+    }
     const uint32_t refine = q->iters + 1 < q->r.n_iter ? 1u : 0u;
     fin_items.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
     for (int d = 0; d < dim; ++d) fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine});
@@ -206,6 +234,16 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
     if ((e2 = launch_serve_init(slots_dev, fin_at(o_init), (int)init_items.size(), max_nb,
                                 stream)) != hipSuccess)
       return e2;
+    for (Req* q : big) {
+      IterLaunch L;
+      L.fid = q->r.integrand_id;
+      L.prec = q->r.prec;
+      L.n_events = q->r.n_events;
+      L.seed = q->r.seed;
+      L.blocks = (int)q->n_chunks;
+      L.threads = q->big_threads;
+      if ((e2 = launch_iterate(q->g, L, q->P, stream)) != hipSuccess) return e2;
+    }
     for (int p = 0; p < 2; ++p)
       for (int c = 0; c < 2; ++c) {
         if (work[p][c].empty()) continue;
@@ -284,6 +322,7 @@ void vegas_srv::run() {
         ++n_active;
         DevGrid g = bind_grid(static_cast<char*>(arena_dev) + q->off, q->r.dim, q->r.n_bins,
                               (int)q->n_chunks, q->r.n_iter);
+        q->g = g;
         SlotDev S{};
         S.t = g.t;
         S.edges = g.edges;
@@ -414,10 +453,26 @@ int vegas_server_submit(vegas_server s, const vegas_request* r, uint64_t* ticket
   if (build_integrand_args(r->integrand_id, r->dim, q->params.data(), r->n_params, &q->P) !=
       VEGAS_OK)
     return VEGAS_EINVAL;
-  q->chunk = chunk_events(r->n_events, s->chunk_fixed);
-  const int64_t nc = (r->n_events + q->chunk - 1) / q->chunk;
-  if (nc > (int64_t)UINT32_MAX / 2) return VEGAS_EINVAL;
-  q->n_chunks = (uint32_t)nc;
+  if (s->chunk_fixed == 0 && r->n_events >= kServeBigEvents) {
+    // one launch of the iteration kernel per iteration, its launch shape a
+    // function of the request alone (so its estimate does not depend on the
+    // mix); its workgroup partials take the chunks' place
+    DeviceGuardSrv dg(s->device);
+    const IterKernel k = iterate_kernel(r->integrand_id, r->prec, r->dim, false);
+    const size_t lds = iterate_lds_bytes(r->dim, r->n_bins);
+    const int threads = k ? default_threads(k, lds) : -1;
+    const int blocks = threads > 0 ? default_blocks(k, threads, lds, r->n_events, kMaxBlocks) : -1;
+    if (blocks < 1) return VEGAS_EDEVICE;
+    q->big = true;
+    q->big_threads = threads;
+    q->chunk = 0;
+    q->n_chunks = (uint32_t)blocks;
+  } else {
+    q->chunk = chunk_events(r->n_events, s->chunk_fixed);
+    const int64_t nc = (r->n_events + q->chunk - 1) / q->chunk;
+    if (nc > (int64_t)UINT32_MAX / 2) return VEGAS_EINVAL;
+    q->n_chunks = (uint32_t)nc;
+  }
   q->L = slot_layout(r->dim, r->n_bins, q->n_chunks, r->n_iter);
   if (q->L.total > s->arena.size()) return VEGAS_ENOMEM;
   std::lock_guard<std::mutex> lk(s->mu);

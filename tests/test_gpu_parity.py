@@ -372,3 +372,25 @@ def test_checkpoint_resume(vg):
     with pytest.raises(vg.VegasError):
         vg.vegas_load(b, state[:-8])
     assert vg.vegas_get_iteration(other) == 0
+
+
+def test_rebind_workspace_after_captured_run(vg, orc):
+    """A workspace bound after a run was captured in a hipGraph: the next run
+    of the same configuration works in the new workspace (the graph of the
+    old one is dropped) and matches the oracle, grid included."""
+    import torch
+    wl = W.WORKLOADS["gauss4d"]
+    I_r, s_r, e_r, _ = orc.run(wl.dim, wl.nb, wl.fid, wl.params, wl.n_events, wl.seed,
+                               wl.n_iter, wl.alpha)
+    h = _handle(vg, wl.dim, wl.nb, wl.fid, wl.params)
+    vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+    nbytes = vg.vegas_workspace_bytes(wl.dim, wl.nb)
+    ws2 = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    vg.vegas_bind_workspace(h, (ws2.data_ptr() + 255) & ~255, nbytes)
+    h.workspace = ws2  # the old workspace tensor is released here
+    assert np.max(np.abs(vg.vegas_get_grid(h) - e_r)) < 1e-12  # state moved along
+    vg.vegas_reset(h)
+    I_t, s_t = vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+    assert _close(I_t, I_r), np.max(np.abs(I_t - I_r) / I_r)
+    assert _close(s_t, s_r, rtol=1e-10)
+    assert np.max(np.abs(vg.vegas_get_grid(h) - e_r)) < 1e-12

@@ -104,8 +104,11 @@ def test_admission_by_memory_and_slots(vg):
         vg.vegas_server_wait(srv, tk, 120.0)
     done, _, _, peak = vg.vegas_server_stats(srv)
     assert done == 8 and 1 <= peak <= 2
+    vg.vegas_server_destroy(srv)
+    # with a fixed chunk of 2048 events, the partial slots of 1e10 events per
+    # iteration alone exceed the budget
+    srv = vg.vegas_server_create(budget, 64, 2048)
     with pytest.raises(vg.VegasError) as e:
-        # 38147 chunk partial slots alone exceed the budget
         vg.vegas_server_submit(srv, 12, 100, W.F_GAUSS, [0.2], 10**10, 4, 1.5, 0)
     assert e.value.code == vg.VEGAS_ENOMEM
     vg.vegas_server_destroy(srv)
@@ -173,3 +176,37 @@ def test_graph_replayed_ticks(vg, orc):
         else:
             assert graph_ticks == 0
         vg.vegas_server_destroy(srv)
+
+
+def test_large_requests_use_the_iteration_kernel(vg, orc):
+    """Requests of at least 2^20 events per iteration run as launches of the
+    single-integral iteration kernel: FP64 matches the oracle at 1e-12, and
+    the result is the same alone, in a mix of small and large requests, and
+    through the handle path."""
+    big64 = W.Request(0, 0.0, 6, 40, W.F_GAUSS, [0.2], 2_000_003, 4, 1.5, 21, W.FP64)
+    big32 = W.Request(1, 0.0, 4, 100, W.F_LO_TOY, [13000.0, 91.19, 2.5, 20.0], 1_500_000, 3,
+                      1.5, 5, W.FP32_EVAL)
+    small = W.serving_trace(30, rate_per_s=1e9, seed=11, max_events=200_000)
+    I_r, s_r, _, _ = orc.run(big64.dim, big64.nb, big64.fid, big64.params, big64.n_events,
+                             big64.seed, big64.n_iter, big64.alpha)
+    res = {}
+    for mix in (False, True):
+        srv = vg.vegas_server_create(1 << 30, 64)
+        reqs = ([big64, big32] + list(small)) if mix else [big64, big32]
+        tickets = [_submit(vg, srv, r) for r in reqs]
+        for tk in tickets:
+            vg.vegas_server_wait(srv, tk, 300.0)
+        res[mix] = [vg.vegas_server_iterations(srv, tickets[i], reqs[i].n_iter) for i in (0, 1)]
+        vg.vegas_server_destroy(srv)
+    I_a, s_a = res[False][0]
+    assert np.all(np.abs(I_a - I_r) <= 1e-12 * np.abs(I_r)), (I_a - I_r) / I_r
+    assert np.all(np.abs(s_a - s_r) <= 1e-10 * s_r)
+    for i in (0, 1):
+        (Ia, sa), (Im, sm) = res[False][i], res[True][i]
+        assert np.all(np.abs(Im - Ia) <= 1e-13 * np.abs(Ia)), (i, Im - Ia)
+        assert np.all(np.abs(sm - sa) <= 1e-11 * sa)
+    h = vg.vegas_create(big32.dim, big32.nb)
+    vg.vegas_set_params(h, big32.fid, big32.params)
+    vg.vegas_set_precision(h, big32.prec)
+    I_h, s_h = vg.vegas_run(h, big32.fid, big32.n_events, big32.seed, big32.n_iter, big32.alpha)
+    assert np.all(np.abs(res[False][1][0] - I_h) <= 1e-13 * np.abs(I_h))
