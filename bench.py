@@ -377,11 +377,12 @@ def small_latency(vg, W, reps):
             "p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3}
 
 
-def replay(vg, W, trace, rate, max_slots, budget=4 << 30):
+def replay(vg, W, trace, rate, max_slots, budget=4 << 30, graph=False):
     """Submit the trace at `rate` requests/s (inf: all at once) to a server
     with `max_slots` slots; returns latency percentiles and throughput."""
     import threading
     srv = vg.vegas_server_create(budget, max_slots)
+    vg.vegas_server_set_graph(srv, graph)
     # warm the server's kernels outside the measurement
     warm = vg.vegas_server_submit(srv, 3, 20, W.F_GAUSS, [0.2], 10_000, 2, 1.5, 0)
     vg.vegas_server_wait(srv, warm)
@@ -433,7 +434,8 @@ def serving_section(vg, W, n_requests):
                     "Breit-Wigner x flat, FP32-eval; trace seed 0",
            "total_events": int(sum(r.n_events * r.n_iter for r in trace))}
     modes = {"batched": 256, "one_at_a_time": 1}
-    rates = [200.0, 1000.0, 3000.0, 5000.0, 10000.0, float("inf")]
+    rates = [200.0, 500.0, 1000.0, 1500.0, 2000.0, 3000.0, 4000.0, 6000.0, 8000.0, 10000.0,
+             float("inf")]
     for mode, slots in modes.items():
         rows = []
         for rate in rates:
@@ -446,10 +448,23 @@ def serving_section(vg, W, n_requests):
     for mode in modes:
         ok = [r for r in res[mode] if r["p99_ms"] <= slo]
         best[mode] = max((r["events_per_s"] for r in ok), default=0.0)
+    # the same server with repeated ticks replayed from captured hipGraphs
+    log("serving batched at 1000/s with graph replays")
+    res["batched_graph_replays_1000_per_s"] = replay(vg, W, trace, 1000.0, 256, graph=True)
     res["p99_slo_ms"] = slo
     res["throughput_at_slo_events_per_s"] = best
     res["batched_over_one_at_a_time_at_slo"] = (best["batched"] / best["one_at_a_time"]
                                                 if best["one_at_a_time"] > 0 else None)
+    # the same comparison at fixed p99 objectives
+    table = []
+    for target in (1.0, 2.0, 5.0, 10.0, 20.0):
+        row = {"p99_ms": target}
+        for mode in modes:
+            ok = [r for r in res[mode] if r["p99_ms"] <= target]
+            row[mode] = max((r["events_per_s"] for r in ok), default=0.0)
+        row["ratio"] = row["batched"] / row["one_at_a_time"] if row["one_at_a_time"] else None
+        table.append(row)
+    res["throughput_at_p99_objectives"] = table
     return res
 
 

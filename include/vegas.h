@@ -328,9 +328,10 @@ int vegas_server_stats(vegas_server s, int64_t *completed, int64_t *events, int6
 /* The server advances every admitted integral by one iteration per tick.
  * A tick whose work equals the previous tick's (the same integrals, none
  * newly admitted, none at its last iteration) reuses the inputs already on
- * the device; from the third such tick in a row its launches are captured
- * once in a hipGraph and replayed until the work changes. enable = 0 launches
- * every tick's kernels one by one (default 1). */
+ * the device. With enable != 0, once 8 such ticks have followed each other
+ * the tick's launches are captured in a hipGraph and replayed until the work
+ * changes. Default 0: a tick is a few launches and the work changes every
+ * few ticks, so capturing costs more than it saves. */
 int vegas_server_set_graph(vegas_server s, int enable);
 
 /* Ticks run so far and how many of them were hipGraph replays (either

@@ -158,9 +158,12 @@ struct vegas_srv {
   std::atomic<int64_t> ticks{0}, graph_ticks{0};
   // A tick whose inputs equal the previous tick's (same integrals, same
   // chunks, none new) repeats its device work without copying its inputs
-  // again. Once two ticks in a row have repeated, that work is captured in a
-  // hipGraph and replayed until the inputs change.
-  std::atomic<bool> use_graph{true};
+  // again. With use_graph, once kGraphRepeats ticks in a row have repeated,
+  // that work is captured in a hipGraph and replayed until the inputs change
+  // (off by default: a tick is a few launches, and requests change every few
+  // ticks, so capturing costs more than it saves).
+  static constexpr int kGraphRepeats = 8;
+  std::atomic<bool> use_graph{false};
   std::vector<unsigned char> last_in;
   int repeats = 0;
   hipGraphExec_t graph = nullptr;
@@ -267,7 +270,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
     ++repeats;
     const void* bufs[3] = {in_dev.p, out_dev.p, out_pin.p};
     if (graph && (std::memcmp(bufs, graph_bufs, sizeof(bufs)) != 0 || !use_graph)) drop_graph();
-    if (use_graph && !graph && repeats >= 2) {
+    if (use_graph && !graph && repeats >= kGraphRepeats) {
       if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return e;
       const hipError_t ew = enqueue_work();
