@@ -122,14 +122,23 @@ __global__ __launch_bounds__(64) void k_serve_finalize(const SlotDev* slots, con
                   fsm + nb, true);
 }
 
-__global__ __launch_bounds__(64) void k_serve_init(const SlotDev* slots, const FinItem* items,
-                                                   int n_items) {
+// New integrals: f.out indexes their descriptor in `fresh` (the tick's input
+// buffer); the wave of dimension 0 also installs it in slots[f.slot], which
+// the later kernels of the tick read.
+__global__ __launch_bounds__(64) void k_serve_init(SlotDev* slots, const FinItem* items,
+                                                   int n_items, const SlotDev* fresh) {
   extern __shared__ __align__(16) double ism[];
   if ((int)blockIdx.x >= n_items) return;
   const FinItem f = items[blockIdx.x];
-  const SlotDev& S = slots[f.slot];
+  const SlotDev& S = fresh[f.out];
   const int nb = (int)S.nb;
   const int d = f.role;
+  if (d == 0) {
+    static_assert(sizeof(SlotDev) % 4 == 0, "descriptor copied in 32-bit words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&S);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(slots + f.slot);
+    for (int i = threadIdx.x; i < (int)(sizeof(SlotDev) / 4); i += 64) dst[i] = src[i];
+  }
   wg_uniform_dim(nb, S.edges + (size_t)d * (nb + 1), S.copies, S.dim * nb, d,
                  S.rec64 + (size_t)d * nb, S.rec32 + (size_t)d * nb, ism);
   if (d == 0 && threadIdx.x == 0) *S.t = 0;
@@ -160,11 +169,11 @@ hipError_t launch_serve_finalize(const SlotDev* slots, const FinItem* items, int
   return hipGetLastError();
 }
 
-hipError_t launch_serve_init(const SlotDev* slots, const FinItem* items, int n_items, int max_nb,
-                             hipStream_t s) {
+hipError_t launch_serve_init(SlotDev* slots, const FinItem* items, int n_items, int max_nb,
+                             const SlotDev* fresh, hipStream_t s) {
   if (n_items < 1) return hipSuccess;
   hipLaunchKernelGGL(k_serve_init, dim3(n_items), dim3(64), sizeof(double) * (max_nb + 1), s,
-                     slots, items, n_items);
+                     slots, items, n_items, fresh);
   return hipGetLastError();
 }
 

@@ -47,7 +47,8 @@ struct WorkItem {
 
 // role < 0: the moments of the slot's iteration (written to out[4*out]);
 // role = d >= 0: histogram reduction of dimension d, then refinement if
-// refine != 0. For k_serve_init, role = d is the dimension to initialise.
+// refine != 0. For k_serve_init, role = d is the dimension to initialise and
+// out the index of the integral's descriptor among the tick's new ones.
 struct FinItem {
   uint32_t slot;
   int32_t role;
@@ -59,7 +60,7 @@ hipError_t launch_serve_iterate(int dmax, int prec, const SlotDev* slots, const 
                                 int n_items, int max_lds, hipStream_t s);
 hipError_t launch_serve_finalize(const SlotDev* slots, const FinItem* items, int n_items,
                                  int max_nb, double* out, hipStream_t s);
-hipError_t launch_serve_init(const SlotDev* slots, const FinItem* items, int n_items, int max_nb,
-                             hipStream_t s);
+hipError_t launch_serve_init(SlotDev* slots, const FinItem* items, int n_items, int max_nb,
+                             const SlotDev* fresh, hipStream_t s);
 
 }  // namespace vegas

@@ -127,6 +127,29 @@ struct DevBuf {
   }
 };
 
+// Pinned host memory mapped into the device's address space (coherent), for
+// results that a kernel writes and the host reads after synchronising.
+struct MappedOut {
+  double* host = nullptr;
+  double* dev = nullptr;
+  size_t n = 0;
+  hipError_t reserve(size_t want) {
+    if (want <= n) return hipSuccess;
+    if (host) (void)hipHostFree(host);
+    host = dev = nullptr;
+    n = 0;
+    const size_t cap = want + want / 2 + 64;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host), cap * sizeof(double),
+                                 hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&dev), host, 0);
+    if (e == hipSuccess) n = cap;
+    return e;
+  }
+  ~MappedOut() {
+    if (host) (void)hipHostFree(host);
+  }
+};
+
 }  // namespace
 
 struct vegas_srv {
@@ -140,8 +163,11 @@ struct vegas_srv {
   SlotDev* slots_pin = nullptr;  // per-slot staging of descriptors
   Pinned<unsigned char> in_pin;  // one tick's host-to-device inputs
   DevBuf<unsigned char> in_dev;
-  Pinned<double> out_pin;
-  DevBuf<double> out_dev;
+  MappedOut out;                 // per-tick results, written by the finalize kernel
+  // tick lists, kept between ticks to reuse their storage
+  std::vector<FinItem> init_items, fin_items;
+  std::vector<WorkItem> work[2][2];  // [prec][dim class 16 / 32]
+  std::vector<Req*> fresh, big;
 
   std::thread worker;
   std::mutex mu;
@@ -178,19 +204,23 @@ struct vegas_srv {
 };
 
 hipError_t vegas_srv::tick(std::vector<Req*>& act) {
-  // ---- host-side tick lists ------------------------------------------------
-  std::vector<FinItem> init_items, fin_items;
-  std::vector<WorkItem> work[2][2];  // [prec][dim class 16 / 32]
+  // ---- host-side tick lists (member vectors: no allocation per tick) --------
+  for (auto& a : work)
+    for (auto& v : a) v.clear();
+  init_items.clear();
+  fin_items.clear();
+  fresh.clear();
+  big.clear();
   int max_lds[2][2] = {{0, 0}, {0, 0}};
   int max_nb = 2;
-  std::vector<Req*> fresh, big;
   for (size_t i = 0; i < act.size(); ++i) {
     Req* q = act[i];
     const int dim = q->r.dim, nb = q->r.n_bins;
     max_nb = std::max(max_nb, nb);
     if (q->fresh) {
+      for (int d = 0; d < dim; ++d)
+        init_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)fresh.size(), 0});
       fresh.push_back(q);
-      for (int d = 0; d < dim; ++d) init_items.push_back(FinItem{(uint32_t)q->slot, d, 0, 0});
     }
     if (q->big) {
       big.push_back(q);
@@ -204,17 +234,22 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
     }
     const uint32_t refine = q->iters + 1 < q->r.n_iter ? 1u : 0u;
     fin_items.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
-    for (int d = 0; d < dim; ++d) fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine});
+    for (int d = 0; d < dim; ++d)
+      fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine});
   }
   // ---- pack the inputs into one pinned buffer ------------------------------
-  size_t bytes = (init_items.size() + fin_items.size()) * sizeof(FinItem);
+  // [finalize items][work items by class] — the part that repeats from tick
+  // to tick — then, for new integrals only, [descriptors][init items].
+  size_t core = fin_items.size() * sizeof(FinItem);
   for (auto& a : work)
-    for (auto& v : a) bytes += v.size() * sizeof(WorkItem);
+    for (auto& v : a) core += v.size() * sizeof(WorkItem);
+  const size_t o_desc = (core + 15) / 16 * 16;
+  const size_t o_init = o_desc + fresh.size() * sizeof(SlotDev);
+  const size_t bytes = fresh.empty() ? core : o_init + init_items.size() * sizeof(FinItem);
   hipError_t e;
   if ((e = in_pin.reserve(bytes)) != hipSuccess) return e;
   if ((e = in_dev.reserve(bytes)) != hipSuccess) return e;
-  if ((e = out_pin.reserve(4 * act.size())) != hipSuccess) return e;
-  if ((e = out_dev.reserve(4 * act.size())) != hipSuccess) return e;
+  if ((e = out.reserve(4 * act.size())) != hipSuccess) return e;
   size_t o = 0;
   auto put = [&](const void* src, size_t n) {
     const size_t at = o;
@@ -222,20 +257,28 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
     o += n;
     return at;
   };
-  const size_t o_init = put(init_items.data(), init_items.size() * sizeof(FinItem));
   const size_t o_fin = put(fin_items.data(), fin_items.size() * sizeof(FinItem));
   size_t o_work[2][2];
   for (int p = 0; p < 2; ++p)
-    for (int c = 0; c < 2; ++c) o_work[p][c] = put(work[p][c].data(), work[p][c].size() * sizeof(WorkItem));
+    for (int c = 0; c < 2; ++c)
+      o_work[p][c] = put(work[p][c].data(), work[p][c].size() * sizeof(WorkItem));
+  if (!fresh.empty()) {
+    o = o_desc;
+    for (Req* q : fresh) put(slots_pin + q->slot, sizeof(SlotDev));
+    put(init_items.data(), init_items.size() * sizeof(FinItem));
+  }
   // ---- device work ------------------------------------------------------------
   auto fin_at = [&](size_t off) { return reinterpret_cast<const FinItem*>(in_dev.p + off); };
   auto work_at = [&](size_t off) { return reinterpret_cast<const WorkItem*>(in_dev.p + off); };
   // everything after the input copy: grids of new integrals, the chunks of
-  // every integral's iteration, closing the iterations, the results copy
+  // every integral's iteration, closing the iterations (whose results the
+  // finalize kernel writes into mapped host memory)
   auto enqueue_work = [&]() -> hipError_t {
     hipError_t e2;
-    if ((e2 = launch_serve_init(slots_dev, fin_at(o_init), (int)init_items.size(), max_nb,
-                                stream)) != hipSuccess)
+    if (!fresh.empty() &&
+        (e2 = launch_serve_init(slots_dev, fin_at(o_init), (int)init_items.size(), max_nb,
+                                reinterpret_cast<const SlotDev*>(in_dev.p + o_desc), stream)) !=
+            hipSuccess)
       return e2;
     for (Req* q : big) {
       IterLaunch L;
@@ -256,19 +299,17 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
             hipSuccess)
           return e2;
       }
-    if ((e2 = launch_serve_finalize(slots_dev, fin_at(o_fin), (int)fin_items.size(), max_nb,
-                                    out_dev.p, stream)) != hipSuccess)
-      return e2;
-    return hipMemcpyAsync(out_pin.p, out_dev.p, 4 * sizeof(double) * act.size(),
-                          hipMemcpyDeviceToHost, stream);
+    return launch_serve_finalize(slots_dev, fin_at(o_fin), (int)fin_items.size(), max_nb, out.dev,
+                                 stream);
   };
   ++ticks;
-  const bool same = fresh.empty() && bytes > 0 && bytes == last_in.size() &&
-                    std::memcmp(in_pin.p, last_in.data(), bytes) == 0;
+  // the repeating part already on the device: no input copy (new integrals'
+  // descriptors and init items, if any, still go)
+  const bool same = fresh.empty() && core > 0 && core == last_in.size() &&
+                    std::memcmp(in_pin.p, last_in.data(), core) == 0;
   if (same) {
-    // the device already holds these inputs (the previous tick copied them)
     ++repeats;
-    const void* bufs[3] = {in_dev.p, out_dev.p, out_pin.p};
+    const void* bufs[3] = {in_dev.p, out.dev, nullptr};
     if (graph && (std::memcmp(bufs, graph_bufs, sizeof(bufs)) != 0 || !use_graph)) drop_graph();
     if (use_graph && !graph && repeats >= kGraphRepeats) {
       if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
@@ -276,7 +317,8 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
       const hipError_t ew = enqueue_work();
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(stream, &g);
-      if (ew == hipSuccess && ec == hipSuccess) e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+      if (ew == hipSuccess && ec == hipSuccess)
+        e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
       if (g) (void)hipGraphDestroy(g);
       if (ew != hipSuccess) return ew;
       if (ec != hipSuccess) return ec;
@@ -296,13 +338,8 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   }
   drop_graph();
   repeats = 0;
-  last_in.assign(in_pin.p, in_pin.p + bytes);
-  for (Req* q : fresh) {
-    if ((e = hipMemcpyAsync(slots_dev + q->slot, slots_pin + q->slot, sizeof(SlotDev),
-                            hipMemcpyHostToDevice, stream)) != hipSuccess)
-      return e;
-    q->fresh = false;
-  }
+  last_in.assign(in_pin.p, in_pin.p + core);
+  for (Req* q : fresh) q->fresh = false;
   if (bytes && (e = hipMemcpyAsync(in_dev.p, in_pin.p, bytes, hipMemcpyHostToDevice, stream)) !=
                    hipSuccess)
     return e;
@@ -384,7 +421,7 @@ void vegas_srv::run() {
     for (size_t i = 0; i < act.size(); ++i) {
       Req* q = act[i];
       work_items += q->n_chunks;
-      const double* r = out_pin.p + 4 * i;
+      const double* r = out.host + 4 * i;
       q->I_t.push_back(r[0]);
       q->s_t.push_back(r[1]);
       q->bad += (int64_t)r[2];
