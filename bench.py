@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="gauss8d")
-    ap.add_argument("--latency-reps", type=int, default=200)
+    ap.add_argument("--latency-reps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -156,6 +156,9 @@ def main():
         del src, dst
     wl = W.WORKLOADS[args.workload]
     events_per_step = wl.n_events * wl.n_iter
+    # the oracle on every host core of the box's share runs first, in forked
+    # processes, before this process touches the GPU
+    cpu_all = None if args.no_cpu else cpu_baseline_all_cores(wl)
     nblk = (wl.dim + 3) // 4
 
     def make(prec):
@@ -185,12 +188,18 @@ def main():
         # kernel durations: the same steps launched one by one with HIP events
         # around every iteration kernel on the handle's stream
         vg.vegas_timing(h, True, True)
+        per_step = []  # average iteration-kernel time of each step
+        k_ms = k_n = 0
         t1 = time.perf_counter()
         for _ in range(args.steps):
             step(h)
+            ms, n = vg.vegas_timing(h, True, True)
+            per_step.append(ms / max(n, 1))
+            k_ms += ms
+            k_n += n
         torch.cuda.synchronize()
         dt_eager = time.perf_counter() - t1
-        k_ms, k_n = vg.vegas_timing(h, False)
+        vg.vegas_timing(h, False)
         # per-iteration latency: one synchronous vegas_iterate (launch, kernels,
         # 32-byte result copy, synchronisation) on the adapted grid
         lat = []
@@ -201,7 +210,7 @@ def main():
         log(f"prec={prec}: {dt / args.steps * 1e3:.3f} ms/step (eager {dt_eager / args.steps * 1e3:.3f}), "
             f"kernel {k_ms / max(k_n, 1) * 1e3:.1f} us, latency p50 {pct(lat, 50) * 1e3:.3f} ms")
         results[prec] = dict(dt=dt, dt_eager=dt_eager, I_t=I_t, s_t=s_t, comb=comb, k_ms=k_ms,
-                             k_n=k_n, lat=lat)
+                             k_n=k_n, lat=lat, per_step=per_step)
         del h
 
     r32, r64 = results[W.FP32_EVAL], results[W.FP64]
@@ -263,16 +272,21 @@ def main():
             "traffic": traffic_from_profile() if wl.name == "gauss8d" else None,
             "valu_per_event_algorithmic": slots,
             "avg_launch_us": k_avg_s * 1e6,
+            "launch_us_p10_p50_p90": [pct(r32["per_step"], q) * 1e3 for q in (10, 50, 90)],
             "launches": r32["k_n"],
             "fp32_flop_frac_of_157TF": (fp32_flops_per_event(wl.dim) * wl.n_events / k_avg_s
                                         / PEAK_FP32_FLOPS) if slots else None,
             "fp64_kernel": {"avg_launch_us": k64_avg_s * 1e6,
+                            "launch_us_p10_p50_p90": [pct(r64["per_step"], q) * 1e3
+                                                      for q in (10, 50, 90)],
                             "frac": (slots64 * wl.n_events / k64_avg_s / PEAK_VALU_SLOTS)
                             if slots64 else None},
         },
     }
     if not args.no_extras:
-        out["latency_ms"]["gauss4d_fp64"] = small_latency(vg, W, args.latency_reps * 5)
+        out["latency_ms"]["gauss4d_fp64"] = small_latency(vg, W, args.latency_reps)
+        if wl.name == "gauss8d":
+            out["one_gpu_share_of_8"] = gpu_share(vg, W, wl, max(20, args.steps // 4))
         out["events_limit_sweep"] = events_limit_sweep(vg, W, wl, max(3, args.steps // 4))
     if wl.fid == W.F_GAUSS and not args.no_extras:
         out["user_integrand"] = user_integrand_section(
@@ -286,6 +300,7 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, r64["I_t"], r64["s_t"])
+        out["cpu_baseline"]["all_cores"] = cpu_all
     if not args.no_serving:
         out["serving"] = serving_section(vg, W, args.serving_requests)
     print(json.dumps(out))
@@ -466,6 +481,62 @@ def serving_section(vg, W, n_requests):
         table.append(row)
     res["throughput_at_p99_objectives"] = table
     return res
+
+
+def _oracle_chunk(args):
+    import oracle
+    e, fid, params, seed, first, count = args
+    w = oracle.weights(e, fid, params, seed, 0, first, count)
+    return float(np.sum(w))
+
+
+def cpu_baseline_all_cores(wl, chunk=1 << 16, per_core=256):
+    """The oracle's per-event work (draw, map, Jacobian, integrand) for the
+    first iteration of the workload on the uniform grid, in 2^16-event chunks
+    spread over one process per core of this machine's share (at most 16)."""
+    import multiprocessing as mp
+    import oracle
+    cores = min(16, len(os.sched_getaffinity(0)))
+    e = oracle.uniform_grid(wl.dim, wl.nb)
+    n_chunks = cores * per_core
+    jobs = [(e, wl.fid, wl.params, wl.seed, i * chunk, chunk) for i in range(n_chunks)]
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_chunk, jobs[:cores])  # start-up outside the timing
+        t0 = time.perf_counter()
+        pool.map(_oracle_chunk, jobs, chunksize=1)
+        dt = time.perf_counter() - t0
+    return {"value": n_chunks * chunk / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
+            "cpu": model,
+            "sample": f"per-event weights (draw, map, Jacobian, integrand) of events 0..{n_chunks * chunk - 1} "
+                      f"of the {wl.name} random stream at iteration 0 on the uniform grid, "
+                      f"{n_chunks} chunks of {chunk} over {cores} processes, {dt:.1f} s"}
+
+
+def gpu_share(vg, W, wl, steps):
+    """One GPU's share of the workload on 8 GPUs (events split by index, one
+    exchange of 2 + D*nb values per iteration not included): N/8 events per
+    iteration, whole FP32-eval runs."""
+    n = wl.n_events // 8
+    h = vg.vegas_create(wl.dim, wl.nb)
+    vg.vegas_set_params(h, wl.fid, wl.params)
+    vg.vegas_set_precision(h, W.FP32_EVAL)
+    for _ in range(5):
+        vg.vegas_reset(h)
+        vg.vegas_run(h, wl.fid, n, wl.seed, wl.n_iter, wl.alpha)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        vg.vegas_reset(h)
+        vg.vegas_run(h, wl.fid, n, wl.seed, wl.n_iter, wl.alpha)
+    dt = (time.perf_counter() - t0) / steps
+    return {"events_per_iteration": n, "ms_per_run": dt * 1e3, "events_per_s": n * wl.n_iter / dt}
 
 
 def cpu_baseline(wl, gpu_I_t, gpu_s_t):
