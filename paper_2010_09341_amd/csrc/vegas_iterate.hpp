@@ -52,12 +52,14 @@ __global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterat
   extern __shared__ __align__(16) unsigned char smem[];
   using Dm = Dims<D_T>;
   const LdsLayout L = a.lds;
+  // the iteration counter (written by the previous finalize) is read first,
+  // so that its memory latency overlaps the clearing of the LDS histogram
+  const uint32_t t = *a.t;
   if constexpr (!DUMP) {
     zero_hist(L, smem);
     __syncthreads();
   }
 
-  const uint32_t t = *a.t;
   const uint32_t lane_off = lane_hist_offset(L);
   uint32_t hb[Dm::kMax];
   if constexpr (D_T > 0) lane_hist_bases<Dm::kMax>(L, (int)a.nb, hb);

@@ -24,10 +24,10 @@ template <int D_T, int FID, int PREC>
 __device__ void serve_chunk(const SlotDev& S, uint32_t chunk, unsigned char* smem) {
   using Dm = Dims<D_T>;
   const LdsLayout L = lds_layout(S.dim, (int)S.nb, kServeCopies, kServeLdsBudget);
+  const uint32_t t = *S.t;  // issued before the LDS clearing it can overlap
   zero_hist(L, smem);
   __syncthreads();
   const void* rec = PREC == kFp64 ? (const void*)S.rec64 : (const void*)S.rec32;
-  const uint32_t t = *S.t;
   const uint32_t lane_off = lane_hist_offset(L);
   const uint64_t begin = (uint64_t)chunk * S.chunk_events;
   uint64_t end = begin + S.chunk_events;
