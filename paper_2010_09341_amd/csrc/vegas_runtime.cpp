@@ -695,9 +695,9 @@ int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, 
   if (rc) return rc;
   if (n_events < 2 || !I || !sigma) return VEGAS_EINVAL;
   IntegrandArgs P;
+  DeviceGuard dg(h->device);  // kernels of run-time integrands load per device
   rc = integrand_args(h, integrand_id, &P);
   if (rc) return rc;
-  DeviceGuard dg(h->device);
   Shape shape;
   rc = shape_for(h, integrand_id, batch_events(h, n_events), &shape);
   if (rc == VEGAS_EDEVICE) return fail(h, hipErrorInvalidValue);
@@ -738,9 +738,9 @@ int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int 
       !(alpha >= 0.0 && alpha <= VEGAS_MAX_ALPHA))
     return VEGAS_EINVAL;
   IntegrandArgs P;
+  DeviceGuard dg(h->device);  // kernels of run-time integrands load per device
   rc = integrand_args(h, integrand_id, &P);
   if (rc) return rc;
-  DeviceGuard dg(h->device);
   Shape shape;
   rc = shape_for(h, integrand_id, batch_events(h, n_events), &shape);
   if (rc == VEGAS_EDEVICE) return fail(h, hipErrorInvalidValue);
@@ -908,10 +908,10 @@ int vegas_dump_weights(vegas_h h, int integrand_id, uint64_t seed, uint64_t firs
   if (rc) return rc;
   if (count < 0 || count > (int64_t(1) << 26) || (count > 0 && !w_out)) return VEGAS_EINVAL;
   IntegrandArgs P;
+  DeviceGuard dg(h->device);  // kernels of run-time integrands load per device
   rc = integrand_args(h, integrand_id, &P);
   if (rc) return rc;
   if (count == 0) return VEGAS_OK;
-  DeviceGuard dg(h->device);
   if (h->dump_n < (size_t)count) {
     if (h->dump_buf) VEGAS_TRY(h, hipFree(h->dump_buf));
     h->dump_buf = nullptr;
