@@ -293,7 +293,8 @@ __device__ inline uint32_t lane_hist_offset(const LdsLayout& L) {
 // hb[d]: LDS byte address of this lane's copy of cell (d, 0), so that bin k
 // of dimension d is at hb[d] + (k << L.cshift) — one instruction per
 // dimension in the event loop, for KMAX registers held across it (used by
-// the kernels for an exact dimension count). The bases pass through an
+// the kernels for an exact dimension count that are not short of
+// registers). The bases pass through an
 // identity DPP move, which the compiler cannot see through: otherwise it
 // folds them back into (d*nb + k) << cshift, two instructions per dimension.
 template <int KMAX>
@@ -324,8 +325,7 @@ __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem,
 // through the vector cache (a few KiB, resident after the first events).
 // Returns w = f(x) * J in binary64 and, in hist[d], the LDS byte address of
 // the histogram entry that dimension d fell into (in this lane's copy: from
-// hb, set by lane_hist_bases, for an exact dimension count, else from
-// lane_off).
+// hb, set by lane_hist_bases, when HOIST, else from lane_off).
 // ---------------------------------------------------------------------------
 // Grid records are read with structured buffer loads: one resource for the
 // whole record table (workgroup-uniform, in scalar registers) whose stride is
@@ -377,7 +377,7 @@ struct std_conditional_rec<kFp64> {
   using type = Rec64;
 };
 
-template <int D_T, int FID, int PREC, class U = NoUser>
+template <int D_T, int FID, int PREC, class U = NoUser, bool HOIST = false>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
                                                int D, uint32_t nb, double nb_pow_d,
                                                float log2_nb_pow_d, const void* rec,
@@ -411,7 +411,7 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const Rec64 g = load_rec64(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec64));
             x[d] = fma(frac, g.w, g.e);
             jac *= g.w;
-            hist[d] = D_T > 0 ? hb[d] + (k << cshift)
+            hist[d] = HOIST ? hb[d] + (k << cshift)
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
           }
         }
@@ -445,7 +445,7 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const Rec32 g = load_rec32(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec32));
             x[d] = fmaf(frac, g.w, g.e);
             wprod *= g.w;
-            hist[d] = D_T > 0 ? hb[d] + (k << cshift)
+            hist[d] = HOIST ? hb[d] + (k << cshift)
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
           }
         }

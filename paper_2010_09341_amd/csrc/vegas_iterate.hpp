@@ -60,16 +60,19 @@ __global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterat
     __syncthreads();
   }
 
+  // per-dimension LDS bases held in registers, except where registers are
+  // short (the kernels built for 256-thread workgroups)
+  constexpr bool kHoist = D_T > 0 && iter_threads_max<D_T, FID, PREC>() == 1024;
   const uint32_t lane_off = lane_hist_offset(L);
   uint32_t hb[Dm::kMax];
-  if constexpr (D_T > 0) lane_hist_bases<Dm::kMax>(L, (int)a.nb, hb);
+  if constexpr (kHoist) lane_hist_bases<Dm::kMax>(L, (int)a.nb, hb);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t hist[Dm::kMax];
 
   if constexpr (DUMP) {
     for (; n < a.n_events; n += stride)
-      a.w_out[n] = event_weight<D_T, FID, PREC, U>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
+      a.w_out[n] = event_weight<D_T, FID, PREC, U, kHoist>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
                                                 a.nb, a.nb_pow_d, a.log2_nb_pow_d, a.rec, hb,
                                                 lane_off, L.cshift, P, hist);
     return;
@@ -77,7 +80,7 @@ __global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterat
     double s1 = 0.0, s2 = 0.0;
     uint32_t bad = 0;
     for (; n < a.n_events; n += stride) {
-      double w = event_weight<D_T, FID, PREC, U>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
+      double w = event_weight<D_T, FID, PREC, U, kHoist>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
                                               a.nb_pow_d, a.log2_nb_pow_d, a.rec, hb, lane_off,
                                               L.cshift, P, hist);
       if (!__builtin_isfinite(w)) {
