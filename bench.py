@@ -132,6 +132,10 @@ def main():
                     help="first run a plain 256 MiB device copy three times, so that a "
                          "counter run can scale FETCH_SIZE/WRITE_SIZE by a known size")
     args = ap.parse_args()
+    from paper_2010_09341_amd import vegas as _vg
+    if not os.path.exists(_vg.LIB_PATH):  # built already unless nothing is
+        from paper_2010_09341_amd import build as _build
+        _build.build()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
