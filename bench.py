@@ -58,8 +58,10 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
         + log2 + add per 4-dimension block (3)
       Gaussian per dimension: subtract + fma = 2
       weight: FP32 log2 split (add, fma, floor, subtract, exp2, two
-        converts, ldexp) = 8; FP64 exp (range reduction and degree-11
-        polynomial, about 22) + the Jacobian constant and product (2) = 24
+        converts, ldexp) = 8; FP64 exp (lower clamp, Cody-Waite reduction:
+        product, rounding and two fmas; degree-13 Taylor polynomial by
+        Horner's rule: 13 fmas; convert and ldexp = 19) + the fma forming
+        its argument and the Jacobian product (2) = 21
       non-finite check (class, two selects, count select + add) = 5;
       moments (w^2, two adds) = 3
     """
@@ -70,7 +72,7 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
     if prec == 1:
         n += -blocks + 3 * blocks + 8
     else:
-        n += -1 + 24
+        n += -1 + 21
     return n
 
 
@@ -82,7 +84,7 @@ def fp32_flops_per_event(dim: int) -> float:
     return dim * 7 + 4
 
 
-KERNEL_SOURCES = ("vegas_device.hpp", "vegas_iterate.hpp", "vegas_types.hpp", "iter_gauss.hip")
+KERNEL_SOURCES = ("vegas_math.hpp", "vegas_device.hpp", "vegas_iterate.hpp", "vegas_types.hpp", "iter_gauss.hip")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_iterate_gauss8d_fp32eval.md")
 
 

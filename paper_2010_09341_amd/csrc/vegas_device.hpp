@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vegas_math.hpp"
 #include "vegas_types.hpp"
 
 namespace vegas {
@@ -141,7 +142,7 @@ __device__ __forceinline__ double integrand_f64(const double* x, int DMAX, int D
         const double z = x[d] - P.c64[d];
         acc += z * z;
       }
-    return exp(P.d[1] - acc * P.d[0]);
+    return exp_f64(P.d[1] - acc * P.d[0]);
   } else if constexpr (FID == kLoToy) {
     const double S = P.d[0], m2 = P.d[1], mG = P.d[2], norm = P.d[3], cut = P.d[4];
     const double x1 = x[0], x2 = x[1];

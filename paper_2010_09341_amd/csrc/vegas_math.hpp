@@ -1,0 +1,42 @@
+// vegas_math.hpp — elementary functions written for the iteration kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace vegas {
+
+// e^x in binary64 (the binary64 Gaussian evaluates one per event). Cody and
+// Waite's reduction: x = n ln2 + r with n = rint(x / ln2), the product n ln2
+// taken in two parts (a head with trailing zero bits, so that n times it is
+// exact, and a tail), |r| <= ln2/2 + tiny; e^r from its Taylor series to
+// degree 13 (truncation below 5e-18 relative), evaluated by Horner's rule;
+// then the scaling by 2^n, which also gives 0 below about -745 and infinity
+// above about 709.8. x below -1100 (-inf included) is taken as -1100, which
+// gives 0; x must not be NaN (it would give 0 too) and x up to 1e9 keeps n in
+// range. Within 3 ulp of e^x (the tests check it against the C library).
+__host__ __device__ inline double exp_f64(double x) {
+  x = fmax(x, -1100.0);
+  const double ln2_hi = 6.93147180369123816490e-01;  // 0x3FE62E42FEE00000
+  const double ln2_lo = 1.90821492927058770002e-10;  // ln2 - ln2_hi
+  const double n = rint(x * 1.44269504088896338700e+00);  // x / ln2
+  double r = fma(-n, ln2_hi, x);
+  r = fma(-n, ln2_lo, r);
+  // 1/k! for k = 13 .. 2
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)n);
+}
+
+}  // namespace vegas

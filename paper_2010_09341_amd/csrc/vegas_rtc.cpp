@@ -26,7 +26,8 @@
 namespace vegas {
 namespace {
 
-// kRtcKernelSource: vegas_types.hpp, vegas_device.hpp and vegas_iterate.hpp
+// kRtcKernelSource: vegas_math.hpp, vegas_types.hpp, vegas_device.hpp and
+// vegas_iterate.hpp
 // with their #include lines blanked (hiprtc supplies the HIP device API).
 #include "vegas_rtc_source.inc"
 
