@@ -392,6 +392,14 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
   const __amdgpu_buffer_rsrc_t rsrc =
       make_rec_rsrc<typename std_conditional_rec<PREC>::type>(rec, rec_bytes);
   if constexpr (PREC == kFp64) {
+    // Up to 8 dimensions every grid record of the event is requested before
+    // any is used, so that the loads overlap each other and the later
+    // blocks' Philox rounds; above that the records of each 4-dimension
+    // block are used within the block (holding all of them would cost more
+    // registers than the overlap gains).
+    constexpr bool kLoadsFirst = Dm::kMax <= 8;
+    double frac[Dm::kMax];
+    Rec64 g[Dm::kMax];
     double x[Dm::kMax];
     double jac = 1.0;
 #pragma unroll
@@ -408,15 +416,25 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             // (rem + 1/2) 2^-32, exact in binary64 (an add with an inline
             // constant and a product by a scalar register: as one fma the
             // two constants cost two register moves per dimension)
-            const double frac = ((double)rem + 0.5) * 0x1p-32;
-            const Rec64 g = load_rec64(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec64));
-            x[d] = fma(frac, g.w, g.e);
-            jac *= g.w;
+            frac[d] = ((double)rem + 0.5) * 0x1p-32;
+            g[d] = load_rec64(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec64));
             hist[d] = HOIST ? hb[d] + (k << cshift)
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
+            if constexpr (!kLoadsFirst) {
+              x[d] = fma(frac[d], g[d].w, g[d].e);
+              jac *= g[d].w;
+            }
           }
         }
       }
+    }
+    if constexpr (kLoadsFirst) {
+#pragma unroll
+      for (int d = 0; d < Dm::kMax; ++d)
+        if (Dm::on(d, D)) {
+          x[d] = fma(frac[d], g[d].w, g[d].e);
+          jac *= g[d].w;
+        }
     }
     // J = prod_d nb * w_d, with nb^D applied once
     return integrand_f64<FID, U>(x, Dm::kMax, D_T > 0 ? D_T : D, P) * (jac * nb_pow_d);
