@@ -546,11 +546,12 @@ def gpu_share(vg, W, wl, steps):
 
 
 def cpu_baseline(wl, gpu_I_t, gpu_s_t):
-    """The FP64 oracle, single-threaded as written, on the first iterations of
-    the same workload (same seed): about 10-20 s of CPU work."""
+    """The FP64 oracle, single-threaded as written, on the same workload
+    (same seed; the whole run of the 8-D Gaussian, about 7 s of CPU work on
+    an EPYC core; the first iterations of the larger workloads)."""
     import oracle
-    n_iter = 5 if wl.n_events >= 10_000_000 else wl.n_iter
     n_ev = min(wl.n_events, 10_000_000)
+    n_iter = wl.n_iter if wl.n_events <= 10_000_000 else 5
     t0 = time.perf_counter()
     I_t, s_t, _, _ = oracle.run(wl.dim, wl.nb, wl.fid, wl.params, n_ev, wl.seed, n_iter,
                                 wl.alpha)
