@@ -35,15 +35,16 @@ constexpr int kIterThreadsMax = 1024;
 
 // Largest workgroup of an iteration kernel. A 1024-thread workgroup keeps 4
 // waves on every SIMD, which caps a thread at 128 VGPRs; kernels that need
-// more (binary64 RAMBO, binary64 above 12 dimensions, the run-time dimension
-// classes) are built for 256-thread workgroups instead, so that they do not
-// spill.
+// more (binary64 RAMBO, binary64 above 12 dimensions and at 11, the run-time
+// dimension classes) are built for 256-thread workgroups instead, so that
+// they do not spill. (The 11-dimension binary64 kernel exceeds 128 VGPRs by a
+// few where the 12-dimension one, scheduled differently, does not.)
 template <int D_T, int FID, int PREC>
 constexpr int iter_threads_max() {
   if (FID == kRambo24) return PREC == kFp64 ? 256 : 1024;
   if (D_T < 0) return 256;
   if (PREC == kFp32Eval) return 1024;
-  return D_T <= 12 ? 1024 : 256;
+  return (D_T <= 10 || D_T == 12) ? 1024 : 256;
 }
 
 template <int D_T, int FID, int PREC, bool DUMP, class U = NoUser>

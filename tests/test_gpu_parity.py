@@ -99,15 +99,16 @@ def test_iterate_fp64(vg, orc, name, dim, nb, fid, params):
     assert vg.vegas_get_iteration(h) == t + 1
 
 
-SHAPES = [(1, 2, 2), (1, 512, 1000), (5, 37, 99_991), (13, 17, 77_777), (32, 64, 50_001),
-          (16, 128, 40_000), (4, 512, 65_536)]
+SHAPES = [(1, 2, 2), (1, 512, 1000), (5, 37, 99_991), (11, 23, 60_001), (12, 20, 30_000),
+          (13, 17, 77_777), (32, 64, 50_001), (16, 128, 40_000), (4, 512, 65_536)]
 
 
 @pytest.mark.parametrize("dim,nb,n", SHAPES)
 def test_iterate_shapes_fp64(vg, orc, dim, nb, n):
     """Gaussian on random grids across shapes: the minimum (1 dim, 2 bins,
     2 events), the bin maximum, dimensions that leave partial Philox blocks,
-    32 dimensions, and the cell maximum dim * nb = 2048."""
+    11 and 12 dimensions (kernels built for different workgroup bounds), 32
+    dimensions, and the cell maximum dim * nb = 2048."""
     rng = np.random.default_rng(dim * 1000 + nb)
     grid = W.random_grid(rng, dim, nb)
     params = [0.3] + list(rng.uniform(0.3, 0.7, dim))
@@ -243,7 +244,7 @@ def test_launch_shape_independence(vg):
 
 def test_workgroup_bound_of_heavy_kernels(vg, orc):
     """Kernels that need more than 128 registers per thread (binary64 above
-    12 dimensions) are built for 256-thread workgroups: asking for 1024
+    12 dimensions and at 11) are built for 256-thread workgroups: asking for 1024
     threads is rejected before any device work, and the handle still runs
     (and matches the oracle) with the default shape."""
     grid = W.random_grid(np.random.default_rng(4), 14, 20)
