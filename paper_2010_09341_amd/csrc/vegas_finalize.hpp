@@ -159,7 +159,7 @@ __device__ inline void wg_refine_dim(int nb, double alpha, double* erow, const d
       else if (p >= 1.0)
         v = 1.0;
       else
-        v = pow((1.0 - p) / (-log(p)), alpha);
+        v = pow_pos((1.0 - p) / (-log_f64(p)), alpha);
       r[i] = v;
     }
     __syncthreads();

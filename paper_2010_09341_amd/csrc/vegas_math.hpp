@@ -39,4 +39,43 @@ __host__ __device__ inline double exp_f64(double x) {
   return ldexp(p, (int)n);
 }
 
+// ln x in binary64 for finite x > 0 (subnormals included). x = m 2^k with
+// m in [1/sqrt2, sqrt2); ln m = 2 atanh(s) with s = (m - 1)/(m + 1),
+// |s| <= 0.1716, from the odd series 2 s (1 + s^2/3 + s^4/5 + ... + s^20/21)
+// (truncation below 2e-18 relative), evaluated by Horner's rule in s^2; then
+// k ln2 added in two parts as in exp_f64. Within 2 ulp of ln x (the tests
+// check it against the C library).
+__host__ __device__ inline double log_f64(double x) {
+  const double ln2_hi = 6.93147180369123816490e-01;  // as in exp_f64
+  const double ln2_lo = 1.90821492927058770002e-10;
+  int k;
+  double m = frexp(x, &k);  // x = m 2^k, m in [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    k -= 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  // 1/(2j+1) for j = 10 .. 1, then 1
+  double q = 1.0 / 21.0;
+  q = fma(q, z, 1.0 / 19.0);
+  q = fma(q, z, 1.0 / 17.0);
+  q = fma(q, z, 1.0 / 15.0);
+  q = fma(q, z, 1.0 / 13.0);
+  q = fma(q, z, 1.0 / 11.0);
+  q = fma(q, z, 1.0 / 9.0);
+  q = fma(q, z, 1.0 / 7.0);
+  q = fma(q, z, 1.0 / 5.0);
+  q = fma(q, z, 1.0 / 3.0);
+  // ln m = 2s + 2s z q
+  const double two_s = 2.0 * s;
+  const double lnm = fma(two_s * z, q, two_s);
+  const double kd = (double)k;
+  return fma(kd, ln2_hi, fma(kd, ln2_lo, lnm));
+}
+
+// x^a for finite x > 0 as e^(a ln x) (the refinement's compression): a few
+// ulp of ln x, times |a ln x|, relative.
+__host__ __device__ inline double pow_pos(double x, double a) { return exp_f64(a * log_f64(x)); }
+
 }  // namespace vegas

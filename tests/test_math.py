@@ -1,8 +1,9 @@
-"""The binary64 exponential the kernels use for the Gaussian weight
-(vegas_math.hpp), built for the host from the same header and checked against
-the C library's exp (through numpy): within 3 ulp wherever the result is a
-normal number, exact at 0, and the right limits (0 far below, infinity above
-709.8)."""
+"""The binary64 functions the kernels use (vegas_math.hpp), built for the
+host from the same header and checked against the C library through numpy:
+exp within 3 ulp wherever the result is a normal number, exact at 0, with the
+right limits (0 far below, infinity above 709.8); log within 2 ulp over the
+whole positive range, subnormals included, exact at 1; x^a as e^(a ln x)
+within a few ulp of ln x times |a ln x|, as the refinement uses it."""
 import os
 import shutil
 import subprocess
@@ -16,22 +17,29 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
 @pytest.fixture(scope="module")
-def exp_f64(tmp_path_factory):
+def mathf(tmp_path_factory):
     if not os.path.exists(HIPCC):
         pytest.skip("hipcc is not installed")
-    exe = str(tmp_path_factory.mktemp("exp") / "exp_test")
+    exe = str(tmp_path_factory.mktemp("math") / "math_test")
     subprocess.run([HIPCC, "-O2", "-I" + CSRC, os.path.join(ROOT, "tests", "helpers",
-                                                              "exp_test.cpp"), "-o", exe],
+                                                              "math_test.cpp"), "-o", exe],
                    check=True, capture_output=True)
 
-    def run(x):
+    def run(op, x, a=None):
         x = np.asarray(x, dtype=np.float64)
-        out = subprocess.run([exe], input="\n".join(repr(float(v)) for v in x), text=True,
-                             check=True, capture_output=True).stdout.split()
-        got = np.array(out, dtype=np.float64).reshape(-1, 2)
-        assert np.array_equal(got[:, 0], x)
-        return got[:, 1]
+        if a is None:
+            lines = [f"{op} {float(v)!r}" for v in x]
+        else:
+            lines = [f"{op} {float(v)!r} {float(w)!r}" for v, w in zip(x, np.broadcast_to(a, x.shape))]
+        out = subprocess.run([exe], input="\n".join(lines), text=True, check=True,
+                             capture_output=True).stdout.split()
+        return np.array(out, dtype=np.float64)
     return run
+
+
+@pytest.fixture(scope="module")
+def exp_f64(mathf):
+    return lambda x: mathf("e", x)
 
 
 def _ulp_error(y, ref):
@@ -68,3 +76,34 @@ def test_exp_subnormal_results(exp_f64):
     x = np.linspace(-744.0, -708.5, 3001)
     y, ref = exp_f64(x), np.exp(x)
     assert np.all(np.abs(y - ref) <= 4 * np.maximum(np.spacing(ref), 5e-324))
+
+
+def test_log_within_2_ulp(mathf):
+    rng = np.random.default_rng(9)
+    x = np.concatenate([
+        np.exp(rng.uniform(-700.0, 700.0, 20_000)),             # the normal range
+        1.0 + rng.uniform(-1e-3, 1e-3, 5_000),                   # ln x near 0
+        rng.uniform(0.0, 1.0, 5_000),                             # where p_i lives
+        np.ldexp(rng.uniform(0.5, 1.0, 2_000), rng.integers(-1074, -1022, 2_000)),  # subnormal
+        np.array([np.finfo(np.float64).max, np.finfo(np.float64).tiny, 5e-324, 2.0, 0.5]),
+    ])
+    x = x[x > 0]
+    y, ref = mathf("l", x), np.log(x)
+    assert mathf("l", [1.0])[0] == 0.0
+    nz = ref != 0
+    assert _ulp_error(y[nz], ref[nz]).max() <= 2.0
+
+
+def test_pow_pos_as_the_refinement_uses_it(mathf):
+    """r = ((1 - p)/(-ln p))^alpha for p in (0, 1) and alpha in [0, 2]: within
+    8 ulp of ln q times |alpha ln q| (plus exp's 3 ulp) of the C library's
+    pow; alpha = 0 gives exactly 1."""
+    rng = np.random.default_rng(10)
+    p = np.concatenate([rng.uniform(0.0, 1.0, 10_000), np.exp(-rng.uniform(0.0, 700.0, 5_000))])
+    p = p[(p > 0) & (p < 1)]
+    q = (1.0 - p) / -np.log(p)
+    alpha = rng.uniform(0.0, 2.0, q.size)
+    y, ref = mathf("p", q, alpha), np.power(q, alpha)
+    bound = 8.0 * np.abs(alpha * np.log(q)) + 3.0
+    assert np.all(_ulp_error(y, ref) <= bound)
+    assert np.all(mathf("p", q[:100], 0.0) == 1.0)
