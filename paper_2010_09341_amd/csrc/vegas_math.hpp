@@ -1,14 +1,17 @@
-// vegas_math.hpp — elementary functions written for the iteration kernels.
+// vegas_math.hpp — binary64 elementary functions written for the kernels
+// (shorter than the general library ones: no special-case handling the
+// kernels do not need).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace vegas {
 
-// e^x in binary64 (the binary64 Gaussian evaluates one per event). Cody and
-// Waite's reduction: x = n ln2 + r with n = rint(x / ln2), the product n ln2
-// taken in two parts (a head with trailing zero bits, so that n times it is
-// exact, and a tail), |r| <= ln2/2 + tiny; e^r from its Taylor series to
+// e^x in binary64 (the binary64 Gaussian evaluates one per event, the
+// refinement one per bin). Cody and Waite's reduction: x = n ln2 + r with
+// n = rint(x / ln2), the product n ln2 taken in two parts (a head with
+// trailing zero bits, so that n times it is exact, and a tail),
+// |r| <= ln2/2 + tiny; e^r from its Taylor series to
 // degree 13 (truncation below 5e-18 relative), evaluated by Horner's rule;
 // then the scaling by 2^n, which also gives 0 below about -745 and infinity
 // above about 709.8. x below -1100 (-inf included) is taken as -1100, which
