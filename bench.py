@@ -444,11 +444,28 @@ def replay(vg, W, trace, rate, max_slots, budget=4 << 30, graph=False):
             "graph_replayed_ticks": graph_ticks}
 
 
+def replay_median(vg, W, trace, rate, max_slots, repeats):
+    """replay() `repeats` times; each figure is the median over the replays
+    (the peak concurrency the largest). A host-side stall of a few
+    milliseconds, seen about once in twenty replays, holds up every integral
+    in flight, so one replay's p99 at a high rate can jump by ~10 ms; the
+    median of three is not moved by one such replay. Each replay's p99 is
+    kept in p99_ms_replays."""
+    runs = [replay(vg, W, trace, rate, max_slots) for _ in range(repeats)]
+    out = dict(runs[0])
+    for k in ("p50_ms", "p99_ms", "mean_ms", "events_per_s", "makespan_s"):
+        out[k] = float(np.median([r[k] for r in runs]))
+    out["peak_concurrent"] = max(r["peak_concurrent"] for r in runs)
+    out["p99_ms_replays"] = [r["p99_ms"] for r in runs]
+    return out
+
+
 def serving_section(vg, W, n_requests):
     """The serving stream (1000 Poisson arrivals at 200/s, mixed integrals),
     batched (up to 256 integrals at once) and one integral at a time, then a
-    rate sweep; the sustained throughput of each mode compared under a p99
-    objective of twice the one-at-a-time p99 at 200/s."""
+    rate sweep (each rate replayed three times, medians); the sustained
+    throughput of each mode compared under a p99 objective of twice the
+    one-at-a-time p99 at 200/s."""
     trace = W.serving_trace(n_requests, rate_per_s=200.0, seed=0)
     res = {"trace": f"{n_requests} requests, Poisson arrivals at 200/s, dims U{{2..12}}, bins "
                     "U{20..100}, events/iteration log-U[1e4, 1e7], 5-10 iterations, Gaussian or "
@@ -461,7 +478,7 @@ def serving_section(vg, W, n_requests):
         rows = []
         for rate in rates:
             log(f"serving {mode} at {rate}/s")
-            rows.append(replay(vg, W, trace, rate, slots))
+            rows.append(replay_median(vg, W, trace, rate, slots, 1 if math.isinf(rate) else 3))
         res[mode] = rows
     # SLO: twice the one-at-a-time p99 at the trace's own rate (200/s)
     slo = 2.0 * res["one_at_a_time"][0]["p99_ms"]

@@ -71,6 +71,8 @@ struct Req {
 // Requests of at least this many events per iteration run as single-integral
 // iteration-kernel launches rather than as chunks of the batched kernel.
 constexpr int64_t kServeBigEvents = int64_t(1) << 20;
+// Upper end of the per-tick buffers reserved when a server is created.
+constexpr size_t kServeReserveBytes = size_t(8) << 20;
 
 struct DeviceGuardSrv {
   int prev = -1;
@@ -466,6 +468,25 @@ int vegas_server_create(size_t mem_budget_bytes, int max_slots, int64_t chunk_ev
     if (s->slots_dev) (void)hipFree(s->slots_dev);
     if (s->arena_dev) (void)hipFree(s->arena_dev);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    return rc;
+  }
+  // The per-tick input and result buffers, sized up front for every slot
+  // busy with default chunking (an integral below kServeBigEvents events has
+  // at most kServeBigEvents / 2048 chunks), up to kServeReserveBytes: growing
+  // them inside a tick means a pinned allocation and a synchronising free,
+  // milliseconds during which every admitted integral waits.
+  const size_t per_slot = sizeof(SlotDev) + (2 * kMaxDim + 1) * sizeof(FinItem) +
+                          (size_t)(kServeBigEvents / 2048) * sizeof(WorkItem) + 16;
+  const size_t in_bytes = std::min(per_slot * (size_t)max_slots, kServeReserveBytes);
+  e = s->in_pin.reserve(in_bytes);
+  if (e == hipSuccess) e = s->in_dev.reserve(in_bytes);
+  if (e == hipSuccess) e = s->out.reserve(4 * (size_t)max_slots);
+  if (e != hipSuccess) {
+    const int rc = e == hipErrorOutOfMemory ? VEGAS_ENOMEM : VEGAS_EDEVICE;
+    (void)hipHostFree(s->slots_pin);
+    (void)hipFree(s->slots_dev);
+    (void)hipFree(s->arena_dev);
+    (void)hipStreamDestroy(s->stream);
     return rc;
   }
   s->arena = Arena(mem_budget_bytes);
