@@ -169,6 +169,22 @@ hipError_t launch_serve_finalize(const SlotDev* slots, const FinItem* items, int
   return hipGetLastError();
 }
 
+// A tick's packed inputs, 16 bytes per thread, from pinned host memory
+// mapped into the device's address space into device memory.
+__global__ __launch_bounds__(256) void k_serve_stage(const uint4* src, uint4* dst, uint32_t n16) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
+}
+
+hipError_t launch_serve_stage(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t n16 = (bytes + 15) / 16;
+  if (n16 == 0) return hipSuccess;
+  if (!src || !dst || n16 > 0xFFFFFFFFu) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_serve_stage, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), (uint32_t)n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_serve_init(SlotDev* slots, const FinItem* items, int n_items, int max_nb,
                              const SlotDev* fresh, hipStream_t s) {
   if (n_items < 1) return hipSuccess;

@@ -62,5 +62,8 @@ hipError_t launch_serve_finalize(const SlotDev* slots, const FinItem* items, int
                                  int max_nb, double* out, hipStream_t s);
 hipError_t launch_serve_init(SlotDev* slots, const FinItem* items, int n_items, int max_nb,
                              const SlotDev* fresh, hipStream_t s);
+// bytes (rounded up to 16; both buffers must hold that many) from src, host
+// memory mapped into the device's address space, to dst in device memory.
+hipError_t launch_serve_stage(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace vegas

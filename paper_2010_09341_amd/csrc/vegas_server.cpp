@@ -92,25 +92,6 @@ Layout slot_layout(int dim, int nb, uint32_t n_chunks, int ring) {
 size_t slot_bytes(const Req* q) { return q->L.total; }
 
 template <class T>
-struct Pinned {
-  T* p = nullptr;
-  size_t n = 0;
-  hipError_t reserve(size_t want) {
-    if (want <= n) return hipSuccess;
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    n = 0;
-    size_t cap = want + want / 2 + 64;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p), cap * sizeof(T), hipHostMallocDefault);
-    if (e == hipSuccess) n = cap;
-    return e;
-  }
-  ~Pinned() {
-    if (p) (void)hipHostFree(p);
-  }
-};
-
-template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
@@ -129,11 +110,13 @@ struct DevBuf {
   }
 };
 
-// Pinned host memory mapped into the device's address space (coherent), for
-// results that a kernel writes and the host reads after synchronising.
-struct MappedOut {
-  double* host = nullptr;
-  double* dev = nullptr;
+// Pinned host memory mapped into the device's address space (coherent): a
+// tick's packed inputs, which the host writes and a kernel reads, and its
+// results, which a kernel writes and the host reads after synchronising.
+template <class T>
+struct Mapped {
+  T* host = nullptr;
+  T* dev = nullptr;
   size_t n = 0;
   hipError_t reserve(size_t want) {
     if (want <= n) return hipSuccess;
@@ -141,13 +124,13 @@ struct MappedOut {
     host = dev = nullptr;
     n = 0;
     const size_t cap = want + want / 2 + 64;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host), cap * sizeof(double),
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host), cap * sizeof(T),
                                  hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&dev), host, 0);
     if (e == hipSuccess) n = cap;
     return e;
   }
-  ~MappedOut() {
+  ~Mapped() {
     if (host) (void)hipHostFree(host);
   }
 };
@@ -163,9 +146,9 @@ struct vegas_srv {
   int64_t chunk_fixed = 0;
   SlotDev* slots_dev = nullptr;
   SlotDev* slots_pin = nullptr;  // per-slot staging of descriptors
-  Pinned<unsigned char> in_pin;  // one tick's host-to-device inputs
+  Mapped<unsigned char> in_pin;  // one tick's inputs, staged into in_dev by a kernel
   DevBuf<unsigned char> in_dev;
-  MappedOut out;                 // per-tick results, written by the finalize kernel
+  Mapped<double> out;            // per-tick results, written by the finalize kernel
   // tick lists, kept between ticks to reuse their storage
   std::vector<FinItem> init_items, fin_items;
   std::vector<WorkItem> work[2][2];  // [prec][dim class 16 / 32]
@@ -249,13 +232,15 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   const size_t o_init = o_desc + fresh.size() * sizeof(SlotDev);
   const size_t bytes = fresh.empty() ? core : o_init + init_items.size() * sizeof(FinItem);
   hipError_t e;
-  if ((e = in_pin.reserve(bytes)) != hipSuccess) return e;
-  if ((e = in_dev.reserve(bytes)) != hipSuccess) return e;
+  // the staging kernel moves whole 16-byte words
+  const size_t staged = (bytes + 15) / 16 * 16;
+  if ((e = in_pin.reserve(staged)) != hipSuccess) return e;
+  if ((e = in_dev.reserve(staged)) != hipSuccess) return e;
   if ((e = out.reserve(4 * act.size())) != hipSuccess) return e;
   size_t o = 0;
   auto put = [&](const void* src, size_t n) {
     const size_t at = o;
-    if (n) std::memcpy(in_pin.p + o, src, n);
+    if (n) std::memcpy(in_pin.host + o, src, n);
     o += n;
     return at;
   };
@@ -308,7 +293,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   // the repeating part already on the device: no input copy (new integrals'
   // descriptors and init items, if any, still go)
   const bool same = fresh.empty() && core > 0 && core == last_in.size() &&
-                    std::memcmp(in_pin.p, last_in.data(), core) == 0;
+                    std::memcmp(in_pin.host, last_in.data(), core) == 0;
   if (same) {
     ++repeats;
     const void* bufs[3] = {in_dev.p, out.dev, nullptr};
@@ -340,11 +325,13 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   }
   drop_graph();
   repeats = 0;
-  last_in.assign(in_pin.p, in_pin.p + core);
+  last_in.assign(in_pin.host, in_pin.host + core);
   for (Req* q : fresh) q->fresh = false;
-  if (bytes && (e = hipMemcpyAsync(in_dev.p, in_pin.p, bytes, hipMemcpyHostToDevice, stream)) !=
-                   hipSuccess)
-    return e;
+  // the inputs reach device memory through a kernel that reads the mapped
+  // host buffer, not through a copy engine: a host-to-device copy of a few
+  // KB now and then took milliseconds to enqueue, holding up every integral
+  // in flight
+  if ((e = launch_serve_stage(in_pin.dev, in_dev.p, bytes, stream)) != hipSuccess) return e;
   if ((e = enqueue_work()) != hipSuccess) return e;
   return hipStreamSynchronize(stream);
 }
