@@ -233,10 +233,11 @@ int vegas_dump_weights(vegas_h h, int integrand_id, uint64_t seed, uint64_t firs
                        double *w_out);
 
 /* Launch shape of the iteration kernel: at most max_blocks workgroups of
- * `threads` threads (64, 128, 256, 512 or 1024). 0 selects the default: of
- * those thread counts, up to the largest the kernel was built for (1024, or
- * 256 for the kernels that need more than 128 registers per thread), the one
- * that keeps the most waves resident, and enough workgroups to fill the GPU.
+ * `threads` threads (a multiple of 64 up to 1024). 0 selects the default: of
+ * the powers of two from 64 up to the largest the kernel was built for
+ * (1024, or 256 for the kernels that need more than 128 registers per
+ * thread), the one that keeps the most waves resident (the largest among
+ * equals), and enough workgroups to fill the GPU.
  * A thread count above what the integrand's kernel was built for makes the
  * next iteration return VEGAS_EINVAL. */
 int vegas_set_launch(vegas_h h, int max_blocks, int threads);

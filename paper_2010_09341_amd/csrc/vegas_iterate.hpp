@@ -31,8 +31,6 @@ struct IterArgsDev {
   uint32_t nb;
 };
 
-constexpr int kIterThreadsMax = 1024;
-
 // Largest workgroup of an iteration kernel. A 1024-thread workgroup keeps 4
 // waves on every SIMD, which caps a thread at 128 VGPRs; kernels that need
 // more (binary64 RAMBO, binary64 above 12 dimensions and at 11, the run-time

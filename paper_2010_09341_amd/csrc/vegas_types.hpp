@@ -81,6 +81,8 @@ __host__ __device__ inline uint32_t lds_bytes(const LdsLayout& L) {
 
 // Workgroup partial slots and result-ring entries per integral.
 constexpr int kMaxBlocks = 4096;
+// Largest workgroup of the iteration kernel (any multiple of 64 up to it).
+constexpr int kIterThreadsMax = 1024;
 constexpr int kRing = 1024;
 
 }  // namespace vegas

@@ -233,13 +233,18 @@ def test_launch_shape_independence(vg):
     same shape gives bitwise the same estimate."""
     grid = W.random_grid(np.random.default_rng(3), 7, 33)
     res = []
-    for blocks, threads in ((0, 0), (0, 0), (7, 64), (1, 256), (300, 128), (0, 512), (3, 1024)):
+    for blocks, threads in ((0, 0), (0, 0), (7, 64), (1, 256), (300, 128), (0, 512), (3, 1024),
+                            (0, 640), (5, 896), (0, 192)):
         h = _handle(vg, 7, 33, W.F_SUM, None, W.FP64, grid)
         vg.vegas_set_launch(h, blocks, threads)
         res.append(vg.vegas_iterate(h, W.F_SUM, 123_457, 9))
     assert res[0] == res[1]
     for I, s in res[2:]:
         assert _close(I, res[0][0], rtol=1e-14)
+    for threads in (-64, 100, 1088):
+        with pytest.raises(vg.VegasError) as e:
+            vg.vegas_set_launch(h, 0, threads)
+        assert e.value.code == vg.VEGAS_EINVAL
 
 
 def test_workgroup_bound_of_heavy_kernels(vg, orc):
