@@ -14,11 +14,13 @@
 //      workgroups), whose workgroups take the place of its chunks;
 //   3. one launch closes all those iterations: moments, histogram reduction
 //      and refinement (k_serve_finalize);
-//   4. the per-integral (I_t, sigma_t) come back in one 32-byte-per-integral
-//      copy; finished integrals free their slot and arena range, which the
-//      next tick can give to waiting requests.
-// Host-to-device inputs of a tick (new slot descriptors, work lists) travel
-// in one copy from pinned memory.
+//   4. the per-integral (I_t, sigma_t) come back through mapped host memory,
+//      32 bytes per integral, which the closing kernel writes; finished
+//      integrals free their slot and arena range, which the next tick can
+//      give to waiting requests.
+// The inputs of a tick (new slot descriptors, work lists) are packed into one
+// pinned buffer mapped into the device's address space, from which a small
+// kernel (k_serve_stage) moves them into device memory.
 #include <hip/hip_runtime_api.h>
 
 #include <atomic>
@@ -257,7 +259,7 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
   // ---- device work ------------------------------------------------------------
   auto fin_at = [&](size_t off) { return reinterpret_cast<const FinItem*>(in_dev.p + off); };
   auto work_at = [&](size_t off) { return reinterpret_cast<const WorkItem*>(in_dev.p + off); };
-  // everything after the input copy: grids of new integrals, the chunks of
+  // everything after staging the inputs: grids of new integrals, the chunks of
   // every integral's iteration, closing the iterations (whose results the
   // finalize kernel writes into mapped host memory)
   auto enqueue_work = [&]() -> hipError_t {
@@ -290,8 +292,8 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
                                  stream);
   };
   ++ticks;
-  // the repeating part already on the device: no input copy (new integrals'
-  // descriptors and init items, if any, still go)
+  // the inputs already on the device (the same integrals and chunks as the
+  // last tick, none new): no staging
   const bool same = fresh.empty() && core > 0 && core == last_in.size() &&
                     std::memcmp(in_pin.host, last_in.data(), core) == 0;
   if (same) {
