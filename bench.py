@@ -51,7 +51,9 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
         block number: 35 each
       event index and loop: 64-bit add (1) + compare (1) = 2
       map per dimension: 32x32->64 product giving bin and remainder (1),
-        fraction (FP32: alignbit + subtract; FP64: convert + fma) (2), LDS
+        fraction (FP32: alignbit + subtract; FP64: alignbit + shift building
+        1 + remainder 2^-32 from its bits, the record holding the shifted
+        bin origin) (2), LDS
         histogram address (1; the grid record is read with the bin as a
         buffer index), x = fma (1), Jacobian product (1) = 6, one product
         fewer per 4-dimension block (FP32) or per event (FP64); FP32 also max

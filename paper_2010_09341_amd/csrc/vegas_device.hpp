@@ -398,7 +398,7 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
     // block are used within the block (holding all of them would cost more
     // registers than the overlap gains).
     constexpr bool kLoadsFirst = Dm::kMax <= 8;
-    double frac[Dm::kMax];
+    double y[Dm::kMax];
     Rec64 g[Dm::kMax];
     double x[Dm::kMax];
     double jac = 1.0;
@@ -413,15 +413,17 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const uint64_t prod = (uint64_t)r.v[i] * nb;
             const uint32_t k = (uint32_t)(prod >> 32);
             const uint32_t rem = (uint32_t)prod;
-            // (rem + 1/2) 2^-32, exact in binary64 (an add with an inline
-            // constant and a product by a scalar register: as one fma the
-            // two constants cost two register moves per dimension)
-            frac[d] = ((double)rem + 0.5) * 0x1p-32;
+            // 1 + rem 2^-32, exact: rem's bits under the exponent of 1.0 (its
+            // top 20 bits in the high word, its low 12 at the top of the low
+            // word); with the record's shifted origin the point is at
+            // fraction (rem + 1/2) 2^-32 of the bin
+            y[d] = __hiloint2double((int)__builtin_amdgcn_alignbit(0x3FFu, rem, 12u),
+                                    (int)(rem << 20));
             g[d] = load_rec64(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec64));
             hist[d] = HOIST ? hb[d] + (k << cshift)
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
             if constexpr (!kLoadsFirst) {
-              x[d] = fma(frac[d], g[d].w, g[d].e);
+              x[d] = fma(y[d], g[d].w, g[d].e);
               jac *= g[d].w;
             }
           }
@@ -429,10 +431,12 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
       }
     }
     if constexpr (kLoadsFirst) {
+      // keeps the scheduler from moving any load below this point
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int d = 0; d < Dm::kMax; ++d)
         if (Dm::on(d, D)) {
-          x[d] = fma(frac[d], g[d].w, g[d].e);
+          x[d] = fma(y[d], g[d].w, g[d].e);
           jac *= g[d].w;
         }
     }

@@ -21,7 +21,7 @@ namespace vegas {
 __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, Rec32* rec32) {
   for (int k = threadIdx.x; k < nb; k += 64) {
     const double lo = e[k], hi = e[k + 1];
-    rec64[k] = Rec64{lo, hi - lo};
+    rec64[k] = Rec64{fma(-(hi - lo), kRec64Shift, lo), hi - lo};
     // binary32 record: the rounded lower edge and the binary32 difference of
     // the rounded edges, so that e + w lands on the rounded upper edge
     const float lo32 = (float)lo, hi32 = (float)hi;
