@@ -51,13 +51,13 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
         block number: 35 each
       event index and loop: 64-bit add (1) + compare (1) = 2
       map per dimension: 32x32->64 product giving bin and remainder (1),
-        fraction (FP32: alignbit + subtract; FP64: alignbit + shift building
-        1 + remainder 2^-32 from its bits, the record holding the shifted
-        bin origin) (2), LDS
-        histogram address (1; the grid record is read with the bin as a
-        buffer index), x = fma (1), Jacobian product (1) = 6, one product
-        fewer per 4-dimension block (FP32) or per event (FP64); FP32 also max
-        + log2 + add per 4-dimension block (3)
+        the factor 1 + remainder 2^-32 (FP64: alignbit + shift; FP32:
+        alignbit, 23 bits) built from the remainder's bits, the grid record
+        holding the bin's origin shifted to match (2 or 1), LDS histogram
+        address (1; the grid record is read with the bin as a buffer index),
+        x = fma (1), Jacobian product (1) = 6 (FP64) or 5 (FP32), one
+        product fewer per 4-dimension block (FP32) or per event (FP64); FP32
+        also max + log2 + add per 4-dimension block (3)
       Gaussian per dimension: subtract + fma = 2
       weight: FP32 log2 split (add, fma, floor, subtract, exp2, two
         converts, ldexp) = 8; FP64 exp (lower clamp, Cody-Waite reduction:
@@ -72,7 +72,7 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
     blocks = (dim + 3) // 4
     n = 39 + 35 * (blocks - 1) + 2 + 8 * dim + 5 + 3
     if prec == 1:
-        n += -blocks + 3 * blocks + 8
+        n += -dim - blocks + 3 * blocks + 8
     else:
         n += -1 + 21
     return n
@@ -80,10 +80,9 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
 
 def fp32_flops_per_event(dim: int) -> float:
     """Binary32 floating-point operations of the FP32-eval Gaussian per event
-    (fma = 2): the fraction subtract (1), map fma (2), width multiply (1),
-    subtract and fma (3) per dimension, and the weight's fma, subtract, exp2
-    (4)."""
-    return dim * 7 + 4
+    (fma = 2): map fma (2), width multiply (1), subtract and fma (3) per
+    dimension, and the weight's fma, subtract, exp2 (4)."""
+    return dim * 6 + 4
 
 
 KERNEL_SOURCES = ("vegas_math.hpp", "vegas_device.hpp", "vegas_iterate.hpp", "vegas_types.hpp", "iter_gauss.hip")

@@ -460,13 +460,12 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const uint64_t prod = (uint64_t)r.v[i] * nb;
             const uint32_t k = (uint32_t)(prod >> 32);
             const uint32_t rem = (uint32_t)prod;
-            // 1 + (rem >> 9) 2^-23 by placing the bits under the exponent of
-            // 1.0, then minus (1 - 2^-24): the centre ((rem >> 9) + 1/2) 2^-23
-            // of a 2^-23 cell, exact in binary32
-            const float frac =
-                __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u)) - 0x1.fffffep-1f;
+            // 1 + (rem >> 9) 2^-23, exact: the bits under the exponent of
+            // 1.0; with the record's shifted origin the point is at the
+            // centre ((rem >> 9) + 1/2) 2^-23 of a 2^-23 cell of the bin
+            const float y = __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u));
             const Rec32 g = load_rec32(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec32));
-            x[d] = fmaf(frac, g.w, g.e);
+            x[d] = fmaf(y, g.w, g.e);
             wprod *= g.w;
             hist[d] = HOIST ? hb[d] + (k << cshift)
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;

@@ -22,12 +22,13 @@ __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, R
   for (int k = threadIdx.x; k < nb; k += 64) {
     const double lo = e[k], hi = e[k + 1];
     rec64[k] = Rec64{fma(-(hi - lo), kRec64Shift, lo), hi - lo};
-    // binary32 record: the rounded lower edge and the binary32 difference of
-    // the rounded edges, so that e + w lands on the rounded upper edge
+    // binary32 record: w the binary32 difference of the rounded edges (the
+    // rounded lower edge plus w is the rounded upper edge), e the rounded
+    // lower edge minus (1 - 2^-24) w, rounded once
     const float lo32 = (float)lo, hi32 = (float)hi;
     Rec32 r;
-    r.e = lo32;
     r.w = (float)((double)hi32 - (double)lo32);
+    r.e = (float)((double)lo32 - (double)r.w * (double)kRec32Shift);
     rec32[k] = r;
   }
 }

@@ -36,12 +36,14 @@ struct IntegrandArgs {
 //   FP32: {e_k, delta_k} with e_k rounded to binary32 and delta_k the
 //         binary32 difference of the rounded edges, so that e_k + delta_k
 //         lands on the rounded e_{k+1}.
-// Grid record of bin k: binary64 {e, w} with w the bin's width and e its
-// lower edge minus (1 - 2^-33) w (kRec64Shift), so that the point at
-// fraction (l + 1/2) 2^-32 of the bin, lower edge + (l + 1/2) 2^-32 w, is
-// e + (1 + l 2^-32) w, and 1 + l 2^-32 is exact from l's bits; binary32
-// {lower edge, width}.
+// Grid record of bin k: {e, w} with w the bin's width and e its lower edge
+// minus (1 - 2^-33) w in binary64 (kRec64Shift), (1 - 2^-24) w in binary32
+// (kRec32Shift), so that the point at fraction (l + 1/2) 2^-32 of the bin
+// (binary32: (l' + 1/2) 2^-23 with l' = l >> 9), lower edge + that fraction
+// times w, is e + (1 + l 2^-32) w (binary32: e + (1 + l' 2^-23) w), whose
+// factor 1 + l 2^-32 is exact from l's bits.
 constexpr double kRec64Shift = 1.0 - 0x1p-33;
+constexpr float kRec32Shift = 1.0f - 0x1p-24f;
 struct Rec64 {
   double e, w;
 };
