@@ -29,6 +29,9 @@ struct IterArgsDev {
   uint32_t seed_lo, seed_hi;
   int dim;
   uint32_t nb;
+  // CUs of the device when the grid is a whole number of workgroups per CU of
+  // whole groups of four waves, else 0 (the order of the event slots)
+  uint32_t slot_cus;
 };
 
 // Largest workgroup of an iteration kernel. A 1024-thread workgroup keeps 4
@@ -65,8 +68,27 @@ __global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterat
   const uint32_t lane_off = lane_hist_offset(L);
   uint32_t hb[Dm::kMax];
   if constexpr (kHoist) lane_hist_bases<Dm::kMax>(L, (int)a.nb, hb);
+  // Grid stride over events, 64 events per wave slot; the order of the slots
+  // decides where a partial last stride runs. With slot_cus = C (the grid is
+  // k workgroups per CU, workgroup b on the CU of b mod C, and four waves in a
+  // row of a workgroup on four different SIMDs) slot s goes to CU s mod C and,
+  // within the CU, runs through the waves four at a time (0-3 of each of its
+  // k workgroups, then 4-7, ...), so that any number of leading slots loads
+  // the SIMDs of all CUs evenly. Otherwise slot s = v * gridDim.x + b, which
+  // spreads over workgroups first.
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t n;
+  {
+    const uint32_t v = threadIdx.x >> 6, b = blockIdx.x;
+    uint32_t s;
+    if (a.slot_cus) {
+      const uint32_t j = b / a.slot_cus, c = b - j * a.slot_cus, k = gridDim.x / a.slot_cus;
+      s = ((((v >> 2) * k + j) << 2) | (v & 3)) * a.slot_cus + c;
+    } else {
+      s = v * gridDim.x + b;
+    }
+    n = (uint64_t)s * 64 + (threadIdx.x & 63);
+  }
   uint32_t hist[Dm::kMax];
 
   if constexpr (DUMP) {

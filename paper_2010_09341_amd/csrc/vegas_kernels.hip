@@ -15,6 +15,7 @@
 // ALU issue (integer multiplies of Philox, map and integrand arithmetic).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "vegas_device.hpp"
@@ -158,6 +159,28 @@ size_t iterate_lds_bytes(int dim, int nb) {
   return lds_bytes(lds_layout(dim, nb, kIterCopies, kIterLdsBudget));
 }
 
+// CUs of the current device (read once per device), 0 if unknown.
+static uint32_t device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  int n = cache[dev].load(std::memory_order_relaxed);
+  if (n < 1) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n < 1)
+      return 0;
+    cache[dev].store(n, std::memory_order_relaxed);
+  }
+  return (uint32_t)n;
+}
+
+// IterArgsDev::slot_cus for a grid: the CU count when the grid is a whole
+// number of workgroups per CU and the workgroups whole groups of four waves.
+static uint32_t slot_cus(int blocks, int threads) {
+  const uint32_t cus = device_cus();
+  return cus && blocks > 0 && (uint32_t)blocks % cus == 0 && threads % 256 == 0 ? cus : 0;
+}
+
 static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   IterArgsDev a;
   a.t = g.t;
@@ -175,6 +198,7 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.nb_pow_d = pow((double)g.nb, (double)g.dim);
   a.log2_nb_pow_d = (float)(g.dim * log2((double)g.nb));
   a.lds = lds_layout(g.dim, g.nb, kIterCopies, kIterLdsBudget);
+  a.slot_cus = slot_cus(L.blocks, L.threads);
   return a;
 }
 
@@ -202,6 +226,7 @@ hipError_t launch_dump(const DevGrid& g, const IterLaunch& L, const IntegrandArg
   const int threads = 256;
   int64_t blocks = (L.count + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;
+  a.slot_cus = slot_cus((int)blocks, threads);
   return launch_kernel(k, (unsigned)blocks, (unsigned)threads, args,
                        iterate_lds_bytes(g.dim, g.nb), s);
 }
