@@ -228,6 +228,32 @@ def test_nonfinite_counted(vg, orc):
     assert np.all(np.isfinite(vg.vegas_get_hist(h)))
 
 
+def test_full_grid_slot_order(vg, orc):
+    """Launches of a whole number of workgroups per CU (the default shape once
+    the events fill the GPU) order the event slots per CU; every event is
+    still drawn exactly once: an iteration with a ragged last stride matches
+    the oracle's estimate and histogram, and a dump on 256 workgroups of 256
+    threads (per-CU order on a 256-CU device), the last one partly empty and
+    the indices crossing 2^32, matches the oracle event by event."""
+    grid = W.random_grid(np.random.default_rng(7), 3, 41)
+    n = 1_300_001  # about 2.5 grid strides of 512 x 1024 threads
+    h = _handle(vg, 3, 41, W.F_GAUSS, [0.25], W.FP64, grid, 4)
+    I, s = vg.vegas_iterate(h, W.F_GAUSS, n, 21)
+    I_r, s_r, h_r, bad_r = orc.iterate(grid, W.F_GAUSS, [0.25], n, 21, 4)
+    assert bad_r == 0
+    assert _close(I, I_r), (I, I_r)
+    assert _close(s, s_r, rtol=1e-10), (s, s_r)
+    assert _close(vg.vegas_get_hist(h), h_r, rtol=1e-12, atol=1e-13 * h_r.max())
+
+    grid6 = W.random_grid(np.random.default_rng(8), 6, 29)
+    seed, t, first, count = (3 << 32) | 5, 2, 2**32 - 30_000, 65_500
+    h6 = _handle(vg, 6, 29, W.F_GAUSS, [0.3], W.FP64, grid6, t)
+    w = vg.vegas_dump_weights(h6, W.F_GAUSS, seed, first, count)
+    w_r = orc.weights(grid6, W.F_GAUSS, [0.3], seed, t, first, count)
+    assert _close(w, w_r, atol=1e-300 + 1e-15 * np.max(np.abs(w_r)))
+    assert np.unique(w).size > count // 2
+
+
 def test_launch_shape_independence(vg):
     """The estimate does not depend on the launch shape beyond rounding; the
     same shape gives bitwise the same estimate."""
