@@ -163,7 +163,7 @@ def main():
         del src, dst
     wl = W.WORKLOADS[args.workload]
     events_per_step = wl.n_events * wl.n_iter
-    # the oracle on every host core of the box's share runs first, in forked
+    # the oracle on every host core available to the process runs first, in forked
     # processes, before this process touches the GPU
     cpu_all = None if args.no_cpu else cpu_baseline_all_cores(wl)
     nblk = (wl.dim + 3) // 4
