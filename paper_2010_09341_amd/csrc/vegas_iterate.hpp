@@ -1,6 +1,6 @@
 // vegas_iterate.hpp — the iteration kernel template: draw (Philox4x32-10 in
 // registers) -> grid map (records in LDS) -> integrand -> sum w, sum w^2
-// (binary64, wave shuffles + LDS) -> w^2 histogram (LDS-private binary64
+// (binary64, DPP wave sums + LDS) -> w^2 histogram (LDS-private binary64
 // atomics, flushed with global binary64 atomics into one of 8 copies chosen by
 // workgroup index, i.e. by XCD under round-robin dispatch).
 //
@@ -119,9 +119,9 @@ __global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterat
     }
 
     __shared__ double red[3][kIterThreadsMax / 64];
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    bad = wave_sum_u32(bad);
+    s1 = wave_total(s1);
+    s2 = wave_total(s2);
+    bad = wave_total_u32(bad);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
       red[0][wid] = s1;
