@@ -4,7 +4,8 @@
 // unit hypercube are drawn through a per-dimension adaptive grid, the integrand
 // is evaluated on them, and the weights w = f(x) * J feed the estimate and the
 // grid's next refinement. Everything here runs per event in registers; the
-// grid records sit in LDS.
+// grid records are read through the vector cache and the w^2 histogram sits
+// in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,18 +55,6 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 // ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // Sum over the 64 lanes of a whole wave (every lane active), returned
 // wave-uniform: within each row of 16 lanes a butterfly of DPP moves (lane
 // xor 1 and xor 2 by quad permutes, then the half-row and row mirrors, which

@@ -58,9 +58,9 @@ __device__ inline void wg_moments(const double* partials, int n_partials, double
       b += v[j].z;
     }
   }
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  b = wave_sum(b);
+  s1 = wave_total(s1);
+  s2 = wave_total(s2);
+  b = wave_total(b);
   if (threadIdx.x == 0) {
     const double I = s1 / N;
     const double var = (s2 / N - I * I) / (N - 1.0);
@@ -148,7 +148,7 @@ __device__ inline void wg_refine_dim(int nb, double alpha, double* erow, const d
   __syncthreads();
   double part = 0.0;
   for (int i = lane; i < nb; i += 64) part += s[i];
-  const double S = wave_sum(part);  // bitwise equal in every lane
+  const double S = wave_total(part);  // bitwise equal in every lane
   if (!(S > 0.0)) {
     for (int i = lane; i <= nb; i += 64) en[i] = eo[i];
   } else {

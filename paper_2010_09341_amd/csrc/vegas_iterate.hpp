@@ -1,5 +1,5 @@
 // vegas_iterate.hpp — the iteration kernel template: draw (Philox4x32-10 in
-// registers) -> grid map (records in LDS) -> integrand -> sum w, sum w^2
+// registers) -> grid map (records through the vector cache) -> integrand -> sum w, sum w^2
 // (binary64, DPP wave sums + LDS) -> w^2 histogram (LDS-private binary64
 // atomics, flushed with global binary64 atomics into one of 8 copies chosen by
 // workgroup index, i.e. by XCD under round-robin dispatch).

@@ -53,9 +53,9 @@ __device__ void serve_chunk(const SlotDev& S, uint32_t chunk, unsigned char* sme
                                w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __shared__ double red[3][kServeThreads / 64];
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  bad = wave_sum_u32(bad);
+  s1 = wave_total(s1);
+  s2 = wave_total(s2);
+  bad = wave_total_u32(bad);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
     red[0][wid] = s1;
