@@ -102,6 +102,42 @@ __device__ __forceinline__ uint32_t wave_total_u32(uint32_t v) {
          (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
 }
 
+// Exclusive prefix sum over the 64 lanes of a whole wave (every lane active):
+// inclusive sums within each row of 16 lanes by DPP row shifts of 1, 2, 4 and
+// 8 (a lane shifted in from outside the row reads 0), then every row offset by
+// the totals of the rows before it (read from lanes 15, 31, 47); the exclusive
+// value is the inclusive one of the lane before in the row, or the offset
+// itself in the row's first lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64_zero(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint64_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
+constexpr int kDppRowShr1 = 0x111;  // lane i <- i - 1 within each row
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
+constexpr int kDppRowShr8 = 0x118;
+
+__device__ __forceinline__ double wave_scan_excl(double v) {
+  double incl = v;
+  incl += dpp_f64_zero<kDppRowShr1>(incl);
+  incl += dpp_f64_zero<kDppRowShr2>(incl);
+  incl += dpp_f64_zero<kDppRowShr4>(incl);
+  incl += dpp_f64_zero<kDppRowShr8>(incl);
+  const double t0 = readlane_f64(incl, 15), t1 = readlane_f64(incl, 31), t2 = readlane_f64(incl, 47);
+  const double p2 = t0 + t1, p3 = p2 + t2;
+  const uint32_t lane = __lane_id(), row = lane >> 4;
+  const double off = row == 0 ? 0.0 : row == 1 ? t0 : row == 2 ? p2 : p3;
+  incl += off;
+  const double prev = dpp_f64_zero<kDppRowShr1>(incl);
+  return (lane & 15u) ? prev : off;
+}
+
 // ---------------------------------------------------------------------------
 // Integrands in binary64. x[0..D) in the unit hypercube.
 // ---------------------------------------------------------------------------

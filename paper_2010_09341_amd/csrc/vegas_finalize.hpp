@@ -118,7 +118,8 @@ __host__ __device__ constexpr int refine_lds_doubles(int nb) { return 3 * (nb + 
 //     (h_{nb-2}+h_{nb-1})/2 at the ends;
 //  2. p_i = s_i / sum s (a dimension with sum 0 keeps its edges);
 //  3. r_i = ((1 - p_i)/(-ln p_i))^alpha (0 for p_i = 0, 1 for p_i = 1);
-//  4. running sums C_k of r (per-lane contiguous segments, then a wave scan);
+//  4. running sums C_k of r (per-lane contiguous segments, then a wave scan by
+//     DPP moves);
 //  5. new edge j where the piecewise-uniform r density reaches j C_nb / nb:
 //     the old bin k is the smallest with C_{k+1} >= j C_nb/nb (binary
 //     search), the position linear inside it;
@@ -169,14 +170,7 @@ __device__ inline void wg_refine_dim(int nb, double alpha, double* erow, const d
     const int hi = lo + seg < nb ? lo + seg : nb;
     double local = 0.0;
     for (int i = lo; i < hi; ++i) local += r[i];
-    double incl = local;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const double v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += v;
-    }
-    double excl = __shfl_up(incl, 1, 64);
-    if (lane == 0) excl = 0.0;
+    const double excl = wave_scan_excl(local);  // S > 0 in every lane: the whole wave is here
     if (lo < nb) {
       double c = excl;
       C[lo] = c;
