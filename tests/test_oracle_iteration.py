@@ -106,6 +106,30 @@ def test_pull_distribution(orc):
     assert 0.75 < pulls.std() < 1.3
 
 
+def test_whole_run_pulls(orc):
+    """Whole runs of the 4-D Gaussian workload (5 iterations x 1e5 events,
+    refinement after each but the last, inverse-variance combination) over 240
+    seeds: the pulls (I - erf(5)^4)/sigma of the combined results have mean 0
+    within 3 standard errors and standard deviation in [0.85, 1.15], and the
+    chi^2 per degree of freedom averages to 1 within [0.85, 1.15]. This pins
+    the multi-iteration run and the combination's sigma through the closed
+    form rather than through the oracle's own formulae."""
+    wl = W.WORKLOADS["gauss4d"]
+    pulls, chi2 = [], []
+    for seed in range(240):
+        I_t, s_t, _, bad = orc.run(wl.dim, wl.nb, wl.fid, wl.params, wl.n_events, seed,
+                                   wl.n_iter, wl.alpha)
+        assert bad == 0
+        I, s, c = orc.combine(I_t, s_t)
+        pulls.append((I - ERF5_4) / s)
+        chi2.append(c)
+    pulls = np.array(pulls)
+    sd = pulls.std(ddof=1)
+    assert abs(pulls.mean()) < 3 * sd / math.sqrt(len(pulls)), (pulls.mean(), sd)
+    assert 0.85 <= sd <= 1.15, sd
+    assert 0.85 <= np.mean(chi2) <= 1.15, np.mean(chi2)
+
+
 def test_combine_matches_weighted_average(orc):
     I_t = np.array([1.0, 1.2, 0.9, 1.05])
     s_t = np.array([0.1, 0.2, 0.05, 0.1])
