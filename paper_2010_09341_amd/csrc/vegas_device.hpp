@@ -406,11 +406,11 @@ __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem,
 // record as the scalar byte offset, so the address costs no vector
 // instruction. The range check (index below the table size) always passes:
 // k < nb.
-typedef uint32_t rec_u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t rec_u32x3 __attribute__((ext_vector_type(3)));
 typedef uint32_t rec_u32x4 __attribute__((ext_vector_type(4)));
-__device__ rec_u32x2 rec_buffer_load_b64(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
+__device__ rec_u32x3 rec_buffer_load_b96(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
                                          int soffset, int aux)
-    __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v3i32");
 __device__ rec_u32x4 rec_buffer_load_b128(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
                                           int soffset, int aux)
     __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
@@ -425,10 +425,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rec_rsrc(const void* rec,
 
 __device__ __forceinline__ Rec32 load_rec32(__amdgpu_buffer_rsrc_t r, uint32_t k,
                                             uint32_t soff) {
-  const rec_u32x2 v = rec_buffer_load_b64(r, (int)k, 0, (int)soff, 0);
+  const rec_u32x3 v = rec_buffer_load_b96(r, (int)k, 0, (int)soff, 0);
   Rec32 g;
   g.e = __uint_as_float(v[0]);
   g.w = __uint_as_float(v[1]);
+  g.L = __uint_as_float(v[2]);
   return g;
 }
 
@@ -452,8 +453,7 @@ struct std_conditional_rec<kFp64> {
 
 template <int D_T, int FID, int PREC, class U = NoUser, bool HOIST = false>
 __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t k0, uint32_t k1,
-                                               int D, uint32_t nb, double nb_pow_d,
-                                               float log2_nb_pow_d, const void* rec,
+                                               int D, uint32_t nb, const void* rec,
                                                const uint32_t* hb, uint32_t lane_off,
                                                uint32_t cshift, const IntegrandArgs& P,
                                                uint32_t* hist) {
@@ -473,6 +473,8 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
     double y[Dm::kMax];
     Rec64 g[Dm::kMax];
     double x[Dm::kMax];
+    // J = prod_d (nb w_d), the factors taken in dimension order
+    const double nbd = (double)nb;
     double jac = 1.0;
 #pragma unroll
     for (int j = 0; j < Dm::kBlocks; ++j) {
@@ -496,7 +498,7 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
             if constexpr (!kLoadsFirst) {
               x[d] = fma(y[d], g[d].w, g[d].e);
-              jac *= g[d].w;
+              jac *= nbd * g[d].w;
             }
           }
         }
@@ -509,22 +511,18 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
       for (int d = 0; d < Dm::kMax; ++d)
         if (Dm::on(d, D)) {
           x[d] = fma(y[d], g[d].w, g[d].e);
-          jac *= g[d].w;
+          jac *= nbd * g[d].w;
         }
     }
-    // J = prod_d nb * w_d, with nb^D applied once
-    return integrand_f64<FID, U>(x, Dm::kMax, D_T > 0 ? D_T : D, P) * (jac * nb_pow_d);
+    return integrand_f64<FID, U>(x, Dm::kMax, D_T > 0 ? D_T : D, P) * jac;
   } else {
     float x[Dm::kMax];
-    // log2 J = sum over 4-dimension blocks of log2(prod of binary32 widths)
-    // + D log2(nb); a block product below the binary32 normal range is
-    // clamped there (such an event's Jacobian is negligible either way)
+    // log2 J = sum_d log2(nb Delta_d): the records' binary64-built terms
     float l2j = 0.f;
 #pragma unroll
     for (int j = 0; j < Dm::kBlocks; ++j) {
       if (Dm::on(4 * j, D)) {
         const Words4 r = philox4x32_10(n_lo, n_hi, t, (uint32_t)j, k0, k1);
-        float wprod = 1.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int d = 4 * j + i;
@@ -538,15 +536,13 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const float y = __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u));
             const Rec32 g = load_rec32(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec32));
             x[d] = fmaf(y, g.w, g.e);
-            wprod *= g.w;
+            l2j = d == 0 ? g.L : l2j + g.L;
             hist[d] = HOIST ? hb[d] + (k << cshift)
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
           }
         }
-        l2j += __builtin_amdgcn_logf(fmaxf(wprod, 0x1p-126f));
       }
     }
-    l2j += log2_nb_pow_d;  // D log2(nb)
     const F32Val v = integrand_f32<FID, U>(x, Dm::kMax, D_T > 0 ? D_T : D, P);
     // w = f * 2^(log2 J + log2 f), the power split into a binary32 mantissa
     // in [1, 2) and an integer exponent applied in binary64.

@@ -17,18 +17,16 @@
 namespace vegas {
 
 // Grid records of bin k = lane, lane+64, ... of dimension row `d` from its
-// edges e[0..nb].
+// edges e[0..nb] (the layouts are those of Rec64 and Rec32).
 __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, Rec32* rec32) {
   for (int k = threadIdx.x; k < nb; k += 64) {
     const double lo = e[k], hi = e[k + 1];
-    rec64[k] = Rec64{fma(-(hi - lo), kRec64Shift, lo), hi - lo};
-    // binary32 record: w the binary32 difference of the rounded edges (the
-    // rounded lower edge plus w is the rounded upper edge), e the rounded
-    // lower edge minus (1 - 2^-24) w, rounded once
-    const float lo32 = (float)lo, hi32 = (float)hi;
+    const double delta = hi - lo;
+    rec64[k] = Rec64{fma(-delta, kRec64Shift, lo), delta};
     Rec32 r;
-    r.w = (float)((double)hi32 - (double)lo32);
-    r.e = (float)((double)lo32 - (double)r.w * (double)kRec32Shift);
+    r.w = (float)delta;
+    r.e = (float)(lo - (double)r.w * (double)kRec32Shift);
+    r.L = (float)log2((double)nb * delta);
     rec32[k] = r;
   }
 }

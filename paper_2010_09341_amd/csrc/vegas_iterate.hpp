@@ -23,8 +23,6 @@ struct IterArgsDev {
   uint64_t n_events;  // events of this launch (dump: number of events to dump)
   uint64_t first;     // index of the launch's first event
   int accumulate;     // add to the workgroup partials of earlier launches
-  double nb_pow_d;    // nb^D, the constant factor of the Jacobian
-  float log2_nb_pow_d;
   LdsLayout lds;
   uint32_t seed_lo, seed_hi;
   int dim;
@@ -48,8 +46,21 @@ constexpr int iter_threads_max() {
   return (D_T <= 10 || D_T == 12) ? 1024 : 256;
 }
 
+// Waves per SIMD a kernel is built to keep resident (the register budget):
+// 8 (64 VGPRs, two 1024-thread workgroups per CU) for the binary32 kernels of
+// up to 9 dimensions, 4 (128 VGPRs) for the binary64 kernels of 9 to 13
+// dimensions, whose event loops fit in that many registers without spilling;
+// otherwise no bound beyond the workgroup size.
+template <int D_T, int FID, int PREC>
+constexpr int iter_min_waves() {
+  if (FID == kRambo24 || D_T < 0) return 1;
+  if (PREC == kFp32Eval) return D_T <= 9 ? 8 : 1;
+  return (D_T >= 9 && D_T <= 13) ? 4 : 1;
+}
+
 template <int D_T, int FID, int PREC, bool DUMP, class U = NoUser>
-__global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterate(
+__global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>()))
+__attribute__((amdgpu_waves_per_eu(iter_min_waves<D_T, FID, PREC>()))) void k_iterate(
     IterArgsDev a, IntegrandArgs P) {
   extern __shared__ __align__(16) unsigned char smem[];
   using Dm = Dims<D_T>;
@@ -94,7 +105,7 @@ __global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterat
   if constexpr (DUMP) {
     for (; n < a.n_events; n += stride)
       a.w_out[n] = event_weight<D_T, FID, PREC, U, kHoist>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim,
-                                                a.nb, a.nb_pow_d, a.log2_nb_pow_d, a.rec, hb,
+                                                a.nb, a.rec, hb,
                                                 lane_off, L.cshift, P, hist);
     return;
   } else {
@@ -102,7 +113,7 @@ __global__ __launch_bounds__((iter_threads_max<D_T, FID, PREC>())) void k_iterat
     uint32_t bad = 0;
     for (; n < a.n_events; n += stride) {
       double w = event_weight<D_T, FID, PREC, U, kHoist>(a.first + n, t, a.seed_lo, a.seed_hi, a.dim, a.nb,
-                                              a.nb_pow_d, a.log2_nb_pow_d, a.rec, hb, lane_off,
+                                              a.rec, hb, lane_off,
                                               L.cshift, P, hist);
       if (!__builtin_isfinite(w)) {
         ++bad;

@@ -195,8 +195,6 @@ static IterArgsDev iter_args(const DevGrid& g, const IterLaunch& L) {
   a.seed_hi = (uint32_t)(L.seed >> 32);
   a.dim = g.dim;
   a.nb = (uint32_t)g.nb;
-  a.nb_pow_d = pow((double)g.nb, (double)g.dim);
-  a.log2_nb_pow_d = (float)(g.dim * log2((double)g.nb));
   a.lds = lds_layout(g.dim, g.nb, kIterCopies, kIterLdsBudget);
   a.slot_cus = slot_cus(L.blocks, L.threads);
   return a;

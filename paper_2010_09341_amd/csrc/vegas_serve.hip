@@ -36,9 +36,8 @@ __device__ void serve_chunk(const SlotDev& S, uint32_t chunk, unsigned char* sme
   uint32_t bad = 0;
   uint32_t hist[Dm::kMax];
   for (uint64_t n = begin + threadIdx.x; n < end; n += blockDim.x) {
-    double w = event_weight<D_T, FID, PREC>(n, t, S.seed_lo, S.seed_hi, S.dim, S.nb, S.nb_pow_d,
-                                            S.log2_nb_pow_d, rec, nullptr, lane_off, L.cshift, S.P,
-                                            hist);
+    double w = event_weight<D_T, FID, PREC>(n, t, S.seed_lo, S.seed_hi, S.dim, S.nb, rec,
+                                            nullptr, lane_off, L.cshift, S.P, hist);
     if (!__builtin_isfinite(w)) {
       ++bad;
       w = 0.0;

@@ -33,10 +33,7 @@ struct SlotDev {
   int fid;
   int prec;
   int ring;
-  double nb_pow_d;
   double alpha;
-  float log2_nb_pow_d;
-  int pad;
   IntegrandArgs P;
 };
 

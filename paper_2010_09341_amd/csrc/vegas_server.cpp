@@ -373,9 +373,7 @@ void vegas_srv::run() {
         S.fid = q->r.integrand_id;
         S.prec = q->r.prec;
         S.ring = q->r.n_iter;
-        S.nb_pow_d = std::pow((double)q->r.n_bins, (double)q->r.dim);
         S.alpha = q->r.alpha;
-        S.log2_nb_pow_d = (float)(q->r.dim * std::log2((double)q->r.n_bins));
         S.P = q->P;
         slots_pin[q->slot] = S;
       }

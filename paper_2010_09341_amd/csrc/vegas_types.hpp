@@ -31,25 +31,29 @@ struct IntegrandArgs {
   int pad[3];
 };
 
-// Grid record of bin k in dimension d.
-//   FP64: {e_k, e_{k+1} - e_k}
-//   FP32: {e_k, delta_k} with e_k rounded to binary32 and delta_k the
-//         binary32 difference of the rounded edges, so that e_k + delta_k
-//         lands on the rounded e_{k+1}.
-// Grid record of bin k: {e, w} with w the bin's width and e its lower edge
-// minus (1 - 2^-33) w in binary64 (kRec64Shift), (1 - 2^-24) w in binary32
-// (kRec32Shift), so that the point at fraction (l + 1/2) 2^-32 of the bin
-// (binary32: (l' + 1/2) 2^-23 with l' = l >> 9), lower edge + that fraction
-// times w, is e + (1 + l 2^-32) w (binary32: e + (1 + l' 2^-23) w), whose
-// factor 1 + l 2^-32 is exact from l's bits.
+// Grid record of bin k in dimension d, whose edges are lo = e_k and
+// hi = e_{k+1} (binary64) and whose width is Delta = hi - lo.
+//   FP64: {e, w} with w = Delta and e = lo - (1 - 2^-33) w (kRec64Shift), so
+//         that the point at fraction (l + 1/2) 2^-32 of the bin, lo + that
+//         fraction times w, is e + (1 + l 2^-32) w, whose factor 1 + l 2^-32
+//         is exact from l's bits.
+//   FP32: {e, w, L} with w = Delta rounded to binary32 (the bin's own width,
+//         not the difference of its rounded edges, so that a bin narrower
+//         than the binary32 spacing at its position keeps its width), e =
+//         lo - (1 - 2^-24) w rounded to binary32 (kRec32Shift: the point at
+//         fraction (l' + 1/2) 2^-23 is e + (1 + l' 2^-23) w), and
+//         L = log2(nb Delta) computed in binary64 and rounded, the bin's
+//         term of log2 of the Jacobian (a sum of these never underflows,
+//         where a product of binary32 widths would).
 constexpr double kRec64Shift = 1.0 - 0x1p-33;
 constexpr float kRec32Shift = 1.0f - 0x1p-24f;
 struct Rec64 {
   double e, w;
 };
-struct alignas(8) Rec32 {
-  float e, w;
+struct alignas(4) Rec32 {
+  float e, w, L;
 };
+static_assert(sizeof(Rec32) == 12, "binary32 grid record is three words");
 
 // LDS of the iteration kernels' workgroups: `copies` histograms of w^2
 // (binary64), interleaved per cell: the entry of cell (d, k) = d * nb + k in

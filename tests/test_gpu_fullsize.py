@@ -1,19 +1,27 @@
 """Parity at the workloads' full sizes, in the launch configuration bench.py
-times (default launch shape, captured-graph runs):
+times (default launch shape, captured-graph runs), against the FP64 oracle's
+own full runs stored in tests/golden/ (written by tests/golden/make_golden.py,
+which calls only the oracle):
 
-- the 8-D Gaussian, 10 iterations x 1e7 events: FP64 matches the oracle's own
-  full run at 1e-12 per iteration; FP32-eval stays within 0.1 sigma of it;
-- the LO toy (10 x 1e8) and RAMBO 2->4 (10 x 5e7): per-event weights sampled
-  across the whole event range on the uniform grid match the oracle one by one,
-  and properties that hold at any size (every dimension's histogram sums to
-  the same S2; FP32-eval and FP64 agree within 0.1 sigma) hold at full size.
+- the 8-D Gaussian (10 iterations x 1e7 events), the LO 2->2 toy (10 x 1e8)
+  and massless 2->4 RAMBO (10 x 5e7), seed 0: FP64 matches every iteration's
+  I at 1e-12 and sigma, the final grid and the combination within the bounds
+  of tests/tolerances.py; FP32-eval stays within 0.1 sigma of every
+  iteration, with sigma within 1 %;
+- per-event weights sampled across the LO toy's and RAMBO's whole event
+  ranges on the uniform grid, one by one: FP64 at 1e-12, FP32-eval to
+  binary32 accuracy.
 """
 import numpy as np
 import pytest
 
+import tolerances as T
+from golden import make_golden as G
 from paper_2010_09341_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+NAMES = ["gauss8d", "lo_toy", "rambo24"]
 
 
 @pytest.fixture(scope="module")
@@ -33,33 +41,53 @@ def _handle(vg, wl, prec):
     return h
 
 
-@pytest.fixture(scope="module")
-def gauss8d_oracle(orc):
-    wl = W.WORKLOADS["gauss8d"]
-    return orc.run(wl.dim, wl.nb, wl.fid, wl.params, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+def _golden(name):
+    rec, I_r, s_r, e_r = G.load(name)
+    wl = W.WORKLOADS[name]
+    assert (rec["dim"], rec["n_bins"], rec["n_events"], rec["n_iter"], rec["seed"]) == \
+        (wl.dim, wl.nb, wl.n_events, wl.n_iter, wl.seed)
+    return wl, I_r, s_r, e_r
 
 
-def test_gauss8d_full_fp64(vg, gauss8d_oracle):
-    wl = W.WORKLOADS["gauss8d"]
-    I_r, s_r, e_r, _ = gauss8d_oracle
+@pytest.mark.parametrize("name", NAMES)
+def test_full_fp64(vg, orc, name):
+    wl, I_r, s_r, e_r = _golden(name)
     h = _handle(vg, wl, W.FP64)
     I_t, s_t = vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
-    assert np.all(np.abs(I_t - I_r) <= 1e-12 * np.abs(I_r)), np.abs(I_t - I_r) / I_r
-    assert np.all(np.abs(s_t - s_r) <= 1e-10 * s_r)
-    assert np.max(np.abs(vg.vegas_get_grid(h) - e_r)) < 1e-12
-
-
-def test_gauss8d_full_fp32_eval(vg, orc, gauss8d_oracle):
-    wl = W.WORKLOADS["gauss8d"]
-    I_r, s_r, _, _ = gauss8d_oracle
-    h = _handle(vg, wl, W.FP32_EVAL)
-    I_t, s_t = vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
-    assert np.all(np.abs(I_t - I_r) < 0.1 * s_r), (I_t - I_r) / s_r
-    assert np.all(np.abs(s_t / s_r - 1) < 1e-2)
+    assert vg.vegas_nonfinite(h) == 0
+    assert T.rel_close(I_t, I_r), T.max_rel(I_t, I_r)
+    assert T.sigma_close(s_t, s_r, I_r, wl.n_events), T.sigma_excess(s_t, s_r, I_r, wl.n_events)
     I, s, _ = vg.vegas_result(h)
     I_o, s_o, _ = orc.combine(I_r, s_r)
-    assert abs(I - I_o) < 0.1 * s_o
-    assert abs(I - W.gauss_closed_form(8, 0.1)) < 4 * s
+    assert T.combine_close(I, s, I_t, s_t, I_o, s_o, wl.n_events), (I, I_o, s, s_o)
+    hist = vg.vegas_get_hist(h)
+    sums = hist.sum(axis=1)
+    assert np.all(np.abs(sums - sums[0]) <= 1e-12 * sums[0])
+    # The stored run does not keep the last refinement's inputs: the final
+    # edges get the refined-edge bound of the GPU's own grid and histogram
+    # before that refinement, which agree with the oracle's to rounding (every
+    # iteration's I does, above).
+    got = vg.vegas_get_grid(h)
+    vg.vegas_reset(h)
+    vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter - 1, wl.alpha)
+    e_prev, h_last = vg.vegas_get_grid(h), vg.vegas_get_hist(h)
+    assert T.edges_close(got, e_r, e_prev, h_last, wl.alpha), \
+        T.edges_excess(got, e_r, e_prev, h_last, wl.alpha)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_full_fp32_eval(vg, orc, name):
+    wl, I_r, s_r, _ = _golden(name)
+    h = _handle(vg, wl, W.FP32_EVAL)
+    I_t, s_t = vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
+    assert vg.vegas_nonfinite(h) == 0
+    assert np.all(np.abs(I_t - I_r) < 0.1 * s_r), (I_t - I_r) / s_r
+    assert np.all(np.abs(s_t / s_r - 1) < 1e-2), s_t / s_r - 1
+    I, s, _ = vg.vegas_result(h)
+    I_o, s_o, _ = orc.combine(I_r, s_r)
+    assert abs(I - I_o) < 0.1 * s_o, (I - I_o) / s_o
+    if name == "gauss8d":
+        assert abs(I - W.gauss_closed_form(8, 0.1)) < 4 * s
 
 
 def _windows(n):
@@ -69,36 +97,22 @@ def _windows(n):
 @pytest.mark.parametrize("name", ["lo_toy", "rambo24"])
 def test_full_size_sampled_weights(vg, orc, name):
     """Per-event weights on the uniform grid at four windows spanning the
-    workload's event range, including its last event: FP64 to 1e-12, FP32-eval
-    to binary32 accuracy."""
+    workload's event range, including its last event: FP64 at 1e-12 relative;
+    FP32-eval within 2e-4 relative (the binary32 map, integrand and log2
+    Jacobian; RAMBO's boost and s_ij products lose a few more bits) plus
+    1e-12 of the largest weight (a binary32 coordinate within an ulp of 1
+    makes the LO toy's (1 - x)^3 lose all its bits, on weights that small),
+    except that a binary32 cut variable within an ulp of its threshold may
+    flip the cut (at most 2 events per window)."""
     wl = W.WORKLOADS[name]
     e = orc.uniform_grid(wl.dim, wl.nb)
-    for prec, rtol in ((W.FP64, 1e-12), (W.FP32_EVAL, 2e-4)):
+    for prec in (W.FP64, W.FP32_EVAL):
         h = _handle(vg, wl, prec)
         for first in _windows(wl.n_events):
             w = vg.vegas_dump_weights(h, wl.fid, wl.seed, first, 2000)
             w_r = orc.weights(e, wl.fid, wl.params, wl.seed, 0, first, 2000)
-            scale = np.max(np.abs(w_r))
-            bad = np.abs(w - w_r) > rtol * np.abs(w_r) + 1e-12 * scale
-            # binary32 may flip a cut decision within an ulp of the threshold
-            assert bad.sum() <= (0 if prec == W.FP64 else 2), (name, prec, first, bad.sum())
-
-
-@pytest.mark.parametrize("name", ["lo_toy", "rambo24"])
-def test_full_size_runs(vg, name):
-    """The whole workload at full size, FP32-eval and FP64 on the same seed."""
-    wl = W.WORKLOADS[name]
-    out = {}
-    for prec in (W.FP32_EVAL, W.FP64):
-        h = _handle(vg, wl, prec)
-        I_t, s_t = vg.vegas_run(h, wl.fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha)
-        hist = vg.vegas_get_hist(h)
-        sums = hist.sum(axis=1)
-        assert np.all(np.abs(sums - sums[0]) <= 1e-12 * sums[0])
-        assert vg.vegas_nonfinite(h) == 0
-        out[prec] = (I_t, s_t, vg.vegas_result(h))
-    I32, s32, (c32, cs32, _) = out[W.FP32_EVAL]
-    I64, s64, (c64, cs64, _) = out[W.FP64]
-    assert np.all(np.abs(I32 - I64) < 0.1 * s64), (I32 - I64) / s64
-    assert np.all(np.abs(s32 / s64 - 1) < 2e-2)
-    assert abs(c32 - c64) < 0.1 * cs64
+            if prec == W.FP64:
+                assert T.weights_close(w, w_r), (name, first, T.max_rel(w, w_r))
+            else:
+                bad = np.abs(w - w_r) > 2e-4 * np.abs(w_r) + 1e-12 * np.max(np.abs(w_r))
+                assert bad.sum() <= 2, (name, first, bad.sum())

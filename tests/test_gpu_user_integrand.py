@@ -12,6 +12,7 @@ import zlib
 import numpy as np
 import pytest
 
+import tolerances as T
 from paper_2010_09341_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -105,8 +106,7 @@ def test_user_weights_fp64(vg, orc, ids, name, key, dim, nb, ref, params):
     h = _handle(vg, ids[key], dim, nb, params, W.FP64, grid, t)
     w = vg.vegas_dump_weights(h, ids[key], seed, first, count)
     w_r = orc.weights(grid, ref, params, seed, t, first, count)
-    assert _close(w, w_r, atol=1e-300 + 1e-15 * np.max(np.abs(w_r))), \
-        np.max(np.abs(w - w_r) / (np.abs(w_r) + 1e-300))
+    assert T.weights_close(w, w_r), T.max_rel(w, w_r)
     assert np.unique(w).size > count // 2
 
 
@@ -122,9 +122,9 @@ def test_user_iterate(vg, orc, ids, name, key, dim, nb, ref, params):
     I, s = vg.vegas_iterate(h, ids[key], n, seed)
     assert vg.vegas_nonfinite(h) == bad_r == 0
     assert _close(I, I_r), (I, I_r)
-    assert _close(s, s_r, rtol=1e-10), (s, s_r)
+    assert T.sigma_close(s, s_r, I_r, n), T.sigma_excess(s, s_r, I_r, n)
     hist = vg.vegas_get_hist(h)
-    assert _close(hist, h_r, atol=1e-13 * h_r.max())
+    assert T.rel_close(hist, h_r), T.max_rel(hist, h_r)
     h32 = _handle(vg, ids[key], dim, nb, params, W.FP32_EVAL, grid, t)
     I32, s32 = vg.vegas_iterate(h32, ids[key], n, seed)
     assert abs(I32 - I_r) < 0.1 * s_r, (I32, I_r, s_r)
@@ -139,21 +139,23 @@ def test_user_run_gauss4d(vg, orc, ids):
     order)."""
     wl = W.WORKLOADS["gauss4d"]
     fid = ids["gauss"]
-    I_r, s_r, e_r, _ = orc.run(wl.dim, wl.nb, wl.fid, wl.params, wl.n_events, wl.seed,
-                               wl.n_iter, wl.alpha)
+    I_r, s_r, e_r, e_prev, h_last = T.oracle_run_steps(orc, wl.dim, wl.nb, wl.fid, wl.params,
+                                                       wl.n_events, wl.seed, wl.n_iter, wl.alpha)
     h = _handle(vg, fid, wl.dim, wl.nb, wl.params, W.FP64)
     runs = []
     for graph in (True, True, False):
         vg.vegas_reset(h)
         vg.vegas_set_graph(h, graph)
         runs.append(vg.vegas_run(h, fid, wl.n_events, wl.seed, wl.n_iter, wl.alpha))
-        assert np.max(np.abs(vg.vegas_get_grid(h) - e_r)) < 1e-12
+        got = vg.vegas_get_grid(h)
+        assert T.edges_close(got, e_r, e_prev, h_last, wl.alpha), \
+            T.edges_excess(got, e_r, e_prev, h_last, wl.alpha)
     I_t, s_t = runs[0]
     assert _close(I_t, I_r), np.max(np.abs(I_t - I_r) / I_r)
-    assert _close(s_t, s_r, rtol=1e-10)
+    assert T.sigma_close(s_t, s_r, I_r, wl.n_events), T.sigma_excess(s_t, s_r, I_r, wl.n_events)
     for I_x, s_x in runs[1:]:
         assert np.all(np.abs(I_x - I_t) <= 1e-13 * np.abs(I_t))
-        assert np.all(np.abs(s_x - s_t) <= 1e-11 * s_t)
+        assert T.sigma_close(s_x, s_t, I_t, wl.n_events)
 
 
 def test_user_rejections(vg, ids):

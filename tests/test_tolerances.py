@@ -1,0 +1,77 @@
+"""The parity bounds of tests/tolerances.py: an alternative but equally valid
+order of the same binary64 arithmetic stays inside them, and a planted error
+just above them fails."""
+import math
+
+import numpy as np
+
+import tolerances as T
+from paper_2010_09341_amd import workloads as W
+
+
+def _rebin_other_order(edges, hist, alpha):
+    """Re-binning with the running sums taken as 64 contiguous segments plus a
+    scan of the segment totals, compression as exp(alpha log q), and a
+    pairwise total: a different rounding order than the oracle's."""
+    out = np.array(edges, dtype=np.float64)
+    for d, h in enumerate(hist):
+        nb = len(h)
+        s = np.empty(nb)
+        s[0] = (h[0] + h[1]) / 2
+        s[-1] = (h[-2] + h[-1]) / 2
+        s[1:-1] = (h[:-2] + h[1:-1] + h[2:]) / 3
+        S = math.fsum(s)
+        if not S > 0:
+            continue
+        p = s / S
+        r = np.zeros(nb)
+        m = (p > 0) & (p < 1)
+        r[m] = np.exp(alpha * np.log((1 - p[m]) / -np.log(p[m])))
+        r[p >= 1] = 1.0
+        seg = -(-nb // 64)
+        C = np.zeros(nb + 1)
+        off = 0.0
+        for lo in range(0, nb, seg):
+            c = off
+            for i in range(lo, min(lo + seg, nb)):
+                c += r[i]
+                C[i + 1] = c
+            off = c
+        delta = C[-1] / nb
+        e = edges[d]
+        for j in range(1, nb):
+            t = j * delta
+            k = int(np.searchsorted(C[1:], t, side="left"))
+            k = min(k, nb - 1)
+            out[d, j] = e[k] + (t - C[k]) / r[k] * (e[k + 1] - e[k])
+    return out
+
+
+def test_refined_edges_bound(orc):
+    for seed, (dim, nb, zeros) in enumerate([(3, 50, 0.0), (2, 512, 0.3), (4, 100, 0.6)]):
+        rng = np.random.default_rng(seed)
+        e = W.random_grid(rng, dim, nb)
+        h = W.random_hist(rng, dim, nb, zeros=zeros)
+        ref = orc.refine(e, h, 1.5)
+        other = _rebin_other_order(e, h, 1.5)
+        tol = T.edges_tol(e, h, 1.5, ref)
+        assert np.all(np.abs(other - ref) <= tol)
+        bad = ref.copy()
+        j = nb // 2
+        bad[0, j] += 2 * tol[0, j]
+        assert not T.edges_close(bad, ref, e, h, 1.5)
+
+
+def test_sigma_bound():
+    # weights that vary little: v small, a large amplification
+    assert T.sigma_rtol(1.0, 1e-6, 10**6) > 1e-9
+    # v of order one: the bound is close to EPS
+    assert T.sigma_rtol(1.0, 1e-3, 10**6) < 3e-12
+    assert T.sigma_close([1.0 + 1e-13], [1.0], 1.0, 10**6)
+    assert not T.sigma_close([1.0 + 1e-11], [1.0], 1.0, 10**6)
+
+
+def test_weights_bound():
+    assert T.weights_close([1.0, 0.0, 1e-310], [1.0 + 5e-13, 0.0, 1e-310 + 1e-325])
+    assert not T.weights_close([1.0 + 2e-12], [1.0])
+    assert not T.weights_close([1e-300], [0.0])
