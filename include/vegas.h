@@ -113,13 +113,18 @@ extern "C" {
 /* ---- limits ------------------------------------------------------------ */
 #define VEGAS_MAX_DIM 32
 #define VEGAS_MAX_BINS 512
-/* dim * n_bins may not exceed this (each workgroup of the iteration kernel
- * keeps up to four copies of the w^2 histogram, 8 bytes per (dimension, bin)
- * each, in at most 64 KiB of LDS; large grids get fewer copies). */
-#define VEGAS_MAX_CELLS 2048
+/* dim * n_bins may not exceed this: each workgroup of the iteration kernel
+ * keeps up to 16 interleaved copies of the w^2 histogram, 8 bytes per
+ * (dimension, bin) each, in at most 64 KiB of LDS; larger grids get fewer
+ * copies, down to one copy of 8192 cells (64 KiB). */
+#define VEGAS_MAX_CELLS 8192
 #define VEGAS_MAX_PARAMS (1 + VEGAS_MAX_DIM)
 /* vegas_run may queue at most this many iterations per call. */
 #define VEGAS_MAX_RUN_ITER 1024
+/* A handle keeps at most this many per-iteration results (behind
+ * vegas_result and in a checkpoint record); vegas_iterate / vegas_run return
+ * VEGAS_ESTATE once it is full, until vegas_reset. */
+#define VEGAS_MAX_HISTORY (1 << 24)
 /* Largest refinement exponent: with 0 <= alpha <= 64 every compressed
  * weight of a non-empty smoothed bin stays a positive binary64 number
  * ((1-p)/(-ln p) >= 1/745 for every positive binary64 p < 1). */
@@ -129,8 +134,13 @@ typedef struct vegas_ctx *vegas_h;
 
 /* Create a handle with the uniform grid e[d][i] = i/n_bins and iteration
  * counter t = 0, on the current GPU, in FP64 mode, with default integrand
- * parameters. 1 <= dim <= VEGAS_MAX_DIM, 2 <= n_bins <= VEGAS_MAX_BINS,
- * dim * n_bins <= VEGAS_MAX_CELLS. *out receives the handle. */
+ * parameters. The grid is Vegas's per-dimension adaptive grid of Sec. 1 (the
+ * paper's VegasFlow(n_dim, n_events) constructor of the Sec. 3.1 listing
+ * takes the dimension; the bin count is Vegas's). 1 <= dim <= VEGAS_MAX_DIM,
+ * 2 <= n_bins <= VEGAS_MAX_BINS, dim * n_bins <= VEGAS_MAX_CELLS. *out
+ * receives the handle (owned by the caller until vegas_destroy). Errors:
+ * VEGAS_EINVAL (shape, NULL out), VEGAS_ENOMEM, VEGAS_EDEVICE; *out is then
+ * NULL. */
 int vegas_create(int dim, int n_bins, vegas_h *out);
 
 /* Release the handle and the device memory it owns. NULL is accepted. */
@@ -165,14 +175,18 @@ int vegas_bind_workspace(vegas_h h, void *dev_ptr, size_t bytes);
 
 /* One iteration (steps draw, map, evaluate, accumulate, histogram) of
  * n_events events (n_events >= 2) with Philox key `seed`, at the handle's
- * iteration counter t; then t += 1. Writes the iteration's estimate *I and
+ * iteration counter t; then t += 1. This is one Vegas iteration of Sec. 1
+ * (importance sampling through the adaptive grid) on the integrand of
+ * Sec. 3.1 (a function of a batch of points of the unit hypercube); the
+ * w^2 histogram it leaves is what informs the next grid (Sec. 3.2). Writes the iteration's estimate *I and
  * its standard deviation *sigma = sqrt((S2/N - I^2)/(N-1)). Non-finite
  * weights are counted, contribute zero, and make the call return
  * VEGAS_ENONFINITE with *I and *sigma still written. Synchronous. */
 int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, double *I,
                   double *sigma);
 
-/* Refine the grid from the histogram of the last iteration: smooth with the
+/* Refine the grid from the histogram of the last iteration (Sec. 3.2: each
+ * iteration informs the grid of the next; the steps are Vegas's, Sec. 1): smooth with the
  * (1,1,1)/3 kernel ((1,1)/2 at the ends), normalise to p_i, compress to
  * r_i = ((1-p_i)/(-ln p_i))^alpha, and place new edges so that every new bin
  * holds an equal share of r (linear inside old bins).
@@ -180,7 +194,8 @@ int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, 
  * VEGAS_ESTATE unless an iteration ran since the last refine. Synchronous. */
 int vegas_refine(vegas_h h, double alpha);
 
-/* A whole run (the paper's run_integration): n_iter iterations from the
+/* A whole run (the paper's run_integration(n_iter) of the Sec. 3.1
+ * listing): n_iter iterations from the
  * current state, refining with alpha after every iteration but the last,
  * queued back to back on the GPU with one synchronisation at the end.
  * I_t[i], sigma_t[i] (host, n_iter entries each, may be NULL) receive the

@@ -149,6 +149,10 @@ int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArg
       a.f[0] = (float)a.d[0];
       a.f[1] = (float)a.d[1];
       a.f[2] = (float)a.d[2];
+      // the binary32 form never applies RAMBO's final scale: its cut and its
+      // weight are carried as c/(2s) and W/(16 s^4)
+      a.f[3] = (float)(a.d[2] / (2.0 * s));
+      a.f[4] = (float)(a.d[1] / (16.0 * s * s * s * s));
       a.mode = (int)mode;
       break;
     }
@@ -477,6 +481,8 @@ hipError_t collect_timing(vegas_h h, size_t n) {
 namespace {
 constexpr uint64_t kStateMagic = 0x5345544147455653ull;  // "SVEGATES"
 constexpr uint32_t kStateVersion = 1;
+// most per-iteration results a record may hold (VEGAS_MAX_HISTORY)
+constexpr uint64_t kMaxHistory = VEGAS_MAX_HISTORY;
 
 struct Writer {
   unsigned char* p;
@@ -544,6 +550,22 @@ int save_state(vegas_h h, Writer& w) {
   w.put_doubles(hist.data(), nh);
   return VEGAS_OK;
 }
+}  // namespace
+
+namespace {
+// Host-side allocations (the per-iteration history, checkpoint buffers,
+// parameter vectors) may throw; no exception crosses the C interface.
+template <class F>
+int no_throw(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return VEGAS_ENOMEM;
+  } catch (...) {
+    return VEGAS_EINVAL;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -626,7 +648,7 @@ int vegas_reset(vegas_h h) {
   return VEGAS_OK;
 }
 
-int vegas_set_params(vegas_h h, int integrand_id, const double* params, int n_params) {
+static int vegas_set_params_body(vegas_h h, int integrand_id, const double* params, int n_params) {
   int rc = ready(h);
   if (rc) return rc;
   if (!integrand_id_ok(integrand_id)) return VEGAS_EINVAL;
@@ -692,11 +714,15 @@ int vegas_bind_workspace(vegas_h h, void* dev_ptr, size_t bytes) {
   return VEGAS_OK;
 }
 
-int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, double* I,
+static int vegas_iterate_body(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, double* I,
                   double* sigma) {
   int rc = ready(h);
   if (rc) return rc;
   if (n_events < 2 || !I || !sigma) return VEGAS_EINVAL;
+  if (h->I_t.size() + 1 > kMaxHistory) return VEGAS_ESTATE;
+  // room for this iteration's result first: a failed allocation changes nothing
+  h->I_t.reserve(h->I_t.size() + 1);
+  h->s_t.reserve(h->s_t.size() + 1);
   IntegrandArgs P;
   DeviceGuard dg(h->device);  // kernels of run-time integrands load per device
   rc = integrand_args(h, integrand_id, &P);
@@ -733,13 +759,16 @@ int vegas_refine(vegas_h h, double alpha) {
   return VEGAS_OK;
 }
 
-int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int n_iter,
+static int vegas_run_body(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int n_iter,
               double alpha, double* I_t, double* sigma_t) {
   int rc = ready(h);
   if (rc) return rc;
   if (n_events < 2 || n_iter < 1 || n_iter > VEGAS_MAX_RUN_ITER ||
       !(alpha >= 0.0 && alpha <= VEGAS_MAX_ALPHA))
     return VEGAS_EINVAL;
+  if (h->I_t.size() + (size_t)n_iter > kMaxHistory) return VEGAS_ESTATE;
+  h->I_t.reserve(h->I_t.size() + n_iter);
+  h->s_t.reserve(h->s_t.size() + n_iter);
   IntegrandArgs P;
   DeviceGuard dg(h->device);  // kernels of run-time integrands load per device
   rc = integrand_args(h, integrand_id, &P);
@@ -946,7 +975,7 @@ int vegas_set_launch(vegas_h h, int max_blocks, int threads) {
   return VEGAS_OK;
 }
 
-int vegas_state_bytes(vegas_h h, size_t* bytes) {
+static int vegas_state_bytes_body(vegas_h h, size_t* bytes) {
   int rc = ready(h);
   if (rc) return rc;
   if (!bytes) return VEGAS_EINVAL;
@@ -956,7 +985,7 @@ int vegas_state_bytes(vegas_h h, size_t* bytes) {
   return VEGAS_OK;
 }
 
-int vegas_save(vegas_h h, void* buf, size_t bytes) {
+static int vegas_save_body(vegas_h h, void* buf, size_t bytes) {
   int rc = ready(h);
   if (rc) return rc;
   size_t need = 0;
@@ -966,7 +995,7 @@ int vegas_save(vegas_h h, void* buf, size_t bytes) {
   return save_state(h, w);
 }
 
-int vegas_load(vegas_h h, const void* buf, size_t bytes) {
+static int vegas_load_body(vegas_h h, const void* buf, size_t bytes) {
   int rc = ready(h);
   if (rc) return rc;
   if (!buf) return VEGAS_EINVAL;
@@ -978,8 +1007,11 @@ int vegas_load(vegas_h h, const void* buf, size_t bytes) {
   const int64_t limit = r.get<int64_t>();
   const uint64_t n_hist = r.get<uint64_t>();
   if (!r.ok || dim != h->dim || nb != h->nb || (prec != VEGAS_FP64 && prec != VEGAS_FP32_EVAL) ||
-      limit < 0 || n_hist > (uint64_t)1 << 32)
+      limit < 0 || n_hist > kMaxHistory)
     return VEGAS_EINVAL;
+  // the record must hold the two n_hist-double arrays before anything is
+  // sized from n_hist (a truncated or corrupt record allocates nothing)
+  if (16 * n_hist > bytes - r.o) return VEGAS_EINVAL;
   std::vector<double> params[VEGAS_N_INTEGRANDS];
   for (int f = 0; f < VEGAS_N_INTEGRANDS; ++f) {
     const uint64_t np = r.get<uint64_t>();
@@ -1044,6 +1076,34 @@ int vegas_timing(vegas_h h, int enable, int reset, double* iterate_ms, int64_t* 
   }
   h->timing = enable != 0;
   return VEGAS_OK;
+}
+
+int vegas_set_params(vegas_h h, int integrand_id, const double* params, int n_params) {
+  return no_throw([&] { return vegas_set_params_body(h, integrand_id, params, n_params); });
+}
+
+int vegas_iterate(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, double* I,
+                  double* sigma) {
+  return no_throw([&] { return vegas_iterate_body(h, integrand_id, n_events, seed, I, sigma); });
+}
+
+int vegas_run(vegas_h h, int integrand_id, int64_t n_events, uint64_t seed, int n_iter,
+              double alpha, double* I_t, double* sigma_t) {
+  return no_throw([&] {
+    return vegas_run_body(h, integrand_id, n_events, seed, n_iter, alpha, I_t, sigma_t);
+  });
+}
+
+int vegas_state_bytes(vegas_h h, size_t* bytes) {
+  return no_throw([&] { return vegas_state_bytes_body(h, bytes); });
+}
+
+int vegas_save(vegas_h h, void* buf, size_t bytes) {
+  return no_throw([&] { return vegas_save_body(h, buf, bytes); });
+}
+
+int vegas_load(vegas_h h, const void* buf, size_t bytes) {
+  return no_throw([&] { return vegas_load_body(h, buf, bytes); });
 }
 
 }  // extern "C"

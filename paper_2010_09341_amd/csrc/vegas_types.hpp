@@ -61,7 +61,9 @@ static_assert(sizeof(Rec32) == 12, "binary32 grid record is three words");
 // l % copies. With 16 copies the 16 lanes that the LDS serves together hit 16
 // distinct bank pairs whatever their bins, so the atomics never conflict
 // (fewer copies for the largest grids, within the kernel's LDS budget; one
-// copy of the largest grid, 2048 cells, takes 16 KiB).
+// copy of the largest grid, 8192 cells, takes 64 KiB, the single-integral
+// kernel's budget; the serving kernel's budget is a target for its copies,
+// and a grid above 4096 cells still gets its one copy there).
 struct LdsLayout {
   uint32_t cells;
   uint32_t copies;  // 1, 2, 4, 8 or 16

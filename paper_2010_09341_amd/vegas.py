@@ -22,7 +22,7 @@ VEGAS_ESTATE, VEGAS_ENONFINITE, VEGAS_EBUSY, VEGAS_ECOMPILE = -4, -5, -6, -7
 VEGAS_FP64, VEGAS_FP32_EVAL = 0, 1
 (VEGAS_F_CONST, VEGAS_F_SUM, VEGAS_F_GAUSS, VEGAS_F_LO_TOY, VEGAS_F_RAMBO24,
  VEGAS_F_BW_FLAT) = range(6)
-VEGAS_MAX_DIM, VEGAS_MAX_BINS, VEGAS_MAX_CELLS = 32, 512, 2048
+VEGAS_MAX_DIM, VEGAS_MAX_BINS, VEGAS_MAX_CELLS = 32, 512, 8192
 VEGAS_MAX_PARAMS, VEGAS_MAX_RUN_ITER = 33, 1024
 VEGAS_F_USER, VEGAS_MAX_USER, VEGAS_MAX_USER_PARAMS = 64, 64, 32
 

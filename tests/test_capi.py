@@ -57,7 +57,7 @@ def test_status_names(L):
 def test_validation_before_device(L):
     h = ctypes.c_void_p()
     EINVAL = -1
-    for dim, nb in ((0, 10), (33, 10), (4, 1), (4, 513), (32, 100), (-1, 5)):
+    for dim, nb in ((0, 10), (33, 10), (4, 1), (4, 513), (32, 300), (17, 512), (-1, 5)):
         assert L.vegas_create(dim, nb, ctypes.byref(h)) == EINVAL
     assert L.vegas_create(4, 10, None) == EINVAL
     n = ctypes.c_size_t()

@@ -97,7 +97,8 @@ def test_iterate_fp64(vg, orc, name, dim, nb, fid, params):
 
 
 SHAPES = [(1, 2, 2), (1, 512, 1000), (5, 37, 99_991), (11, 23, 60_001), (12, 20, 30_000),
-          (13, 17, 77_777), (32, 64, 50_001), (16, 128, 40_000), (4, 512, 65_536)]
+          (13, 17, 77_777), (32, 64, 50_001), (16, 128, 40_000), (4, 512, 65_536),
+          (16, 200, 30_011), (16, 512, 20_000), (32, 256, 12_345)]
 
 
 @pytest.mark.parametrize("dim,nb,n", SHAPES)
@@ -105,7 +106,8 @@ def test_iterate_shapes_fp64(vg, orc, dim, nb, n):
     """Gaussian on random grids across shapes: the minimum (1 dim, 2 bins,
     2 events), the bin maximum, dimensions that leave partial Philox blocks,
     11 and 12 dimensions (kernels built for different workgroup bounds), 32
-    dimensions, and the cell maximum dim * nb = 2048."""
+    dimensions, 2048 cells (four histogram copies in 64 KiB of LDS), 3200
+    cells (two copies) and the cell maximum dim * nb = 8192 (one copy)."""
     rng = np.random.default_rng(dim * 1000 + nb)
     grid = W.random_grid(rng, dim, nb)
     params = [0.3] + list(rng.uniform(0.3, 0.7, dim))
