@@ -253,7 +253,9 @@ __device__ __forceinline__ float rambo24_f32(const float* x, const IntegrandArgs
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const float ct = fminf(fmaf(2.f, x[4 * i], -1.f), 1.f);
-    const float st = __builtin_sqrtf(fmaxf(fmaf(-ct, ct, 1.f), 0.f));
+    // the hardware square root (within an ulp, one instruction; the correctly
+    // rounded one costs a dozen)
+    const float st = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-ct, ct, 1.f), 0.f));
     // v_sin_f32 / v_cos_f32 take their argument in turns: sin(2 pi u) = sin_turns(u)
     const float sp = __builtin_amdgcn_sinf(x[4 * i + 1]);
     const float cp = __builtin_amdgcn_cosf(x[4 * i + 1]);
@@ -470,11 +472,12 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
     // block are used within the block (holding all of them would cost more
     // registers than the overlap gains).
     constexpr bool kLoadsFirst = Dm::kMax <= 8;
-    double y[Dm::kMax];
+    uint32_t rem[Dm::kMax];
     Rec64 g[Dm::kMax];
     double x[Dm::kMax];
-    // J = prod_d (nb w_d), the factors taken in dimension order
-    const double nbd = (double)nb;
+    // J = prod_d (nb Delta_d), the factors taken in dimension order; the
+    // record holds Delta 2^-32, and nb 2^32 is exact
+    const double nbd = (double)nb * 0x1p32;
     double jac = 1.0;
 #pragma unroll
     for (int j = 0; j < Dm::kBlocks; ++j) {
@@ -486,18 +489,14 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
           if (d < Dm::kMax && Dm::on(d, D)) {
             const uint64_t prod = (uint64_t)r.v[i] * nb;
             const uint32_t k = (uint32_t)(prod >> 32);
-            const uint32_t rem = (uint32_t)prod;
-            // 1 + rem 2^-32, exact: rem's bits under the exponent of 1.0 (its
-            // top 20 bits in the high word, its low 12 at the top of the low
-            // word); with the record's shifted origin the point is at
-            // fraction (rem + 1/2) 2^-32 of the bin
-            y[d] = __hiloint2double((int)__builtin_amdgcn_alignbit(0x3FFu, rem, 12u),
-                                    (int)(rem << 20));
+            // the point at fraction (rem + 1/2) 2^-32 of the bin: rem
+            // converts exactly, and the record's e carries the half
+            rem[d] = (uint32_t)prod;
             g[d] = load_rec64(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec64));
             hist[d] = HOIST ? hb[d] + (k << cshift)
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
             if constexpr (!kLoadsFirst) {
-              x[d] = fma(y[d], g[d].w, g[d].e);
+              x[d] = fma((double)rem[d], g[d].w, g[d].e);
               jac *= nbd * g[d].w;
             }
           }
@@ -510,7 +509,7 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
 #pragma unroll
       for (int d = 0; d < Dm::kMax; ++d)
         if (Dm::on(d, D)) {
-          x[d] = fma(y[d], g[d].w, g[d].e);
+          x[d] = fma((double)rem[d], g[d].w, g[d].e);
           jac *= nbd * g[d].w;
         }
     }

@@ -22,7 +22,7 @@ __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, R
   for (int k = threadIdx.x; k < nb; k += 64) {
     const double lo = e[k], hi = e[k + 1];
     const double delta = hi - lo;
-    rec64[k] = Rec64{fma(-delta, kRec64Shift, lo), delta};
+    rec64[k] = Rec64{fma(delta, kRec64Half, lo), delta * kRec64Scale};
     Rec32 r;
     r.w = (float)delta;
     r.e = (float)(lo - (double)r.w * (double)kRec32Shift);

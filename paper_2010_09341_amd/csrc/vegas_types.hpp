@@ -33,10 +33,16 @@ struct IntegrandArgs {
 
 // Grid record of bin k in dimension d, whose edges are lo = e_k and
 // hi = e_{k+1} (binary64) and whose width is Delta = hi - lo.
-//   FP64: {e, w} with w = Delta and e = lo - (1 - 2^-33) w (kRec64Shift), so
-//         that the point at fraction (l + 1/2) 2^-32 of the bin, lo + that
-//         fraction times w, is e + (1 + l 2^-32) w, whose factor 1 + l 2^-32
-//         is exact from l's bits.
+//   FP64: {e, w} with w = Delta 2^-32 (exact) and e = lo + 2^-33 Delta
+//         (rounded once), so that the point at fraction (l + 1/2) 2^-32 of
+//         the bin, lo + that fraction times Delta, is one fma l w + e of the
+//         remainder l converted exactly. e is within half an ulp of a number
+//         no larger than the point, so the point keeps a relative error of a
+//         few ulps wherever it lies in the bin (an origin shifted below lo
+//         instead would cancel against l w near the lower edge of a bin
+//         whose lower edge is small against its width, bin 0 above all).
+//         Widths below 2^-990 lose bits in w (the weight is then below
+//         that times the integrand).
 //   FP32: {e, w, L} with w = Delta rounded to binary32 (the bin's own width,
 //         not the difference of its rounded edges, so that a bin narrower
 //         than the binary32 spacing at its position keeps its width), e =
@@ -45,7 +51,8 @@ struct IntegrandArgs {
 //         L = log2(nb Delta) computed in binary64 and rounded, the bin's
 //         term of log2 of the Jacobian (a sum of these never underflows,
 //         where a product of binary32 widths would).
-constexpr double kRec64Shift = 1.0 - 0x1p-33;
+constexpr double kRec64Half = 0x1p-33;
+constexpr double kRec64Scale = 0x1p-32;
 constexpr float kRec32Shift = 1.0f - 0x1p-24f;
 struct Rec64 {
   double e, w;

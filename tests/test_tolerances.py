@@ -75,3 +75,27 @@ def test_weights_bound():
     assert T.weights_close([1.0, 0.0, 1e-310], [1.0 + 5e-13, 0.0, 1e-310 + 1e-325])
     assert not T.weights_close([1.0 + 2e-12], [1.0])
     assert not T.weights_close([1e-300], [0.0])
+
+
+def test_kappa_bound(orc):
+    """event_kappa is the Gaussian's closed-form condition number
+    sum_d |2 x_d (x_d - c) / a^2|, and the LO toy's weights recomputed at
+    points moved by up to 4 ulps per coordinate (what two correctly rounded
+    maps may differ by) stay inside weights_close with kappa."""
+    rng = np.random.default_rng(3)
+    grid = W.random_grid(rng, 3, 20)
+    x, _, jac = orc.points(grid, 11, 2, 0, 200)
+    kap = T.event_kappa(orc, grid, W.F_GAUSS, [0.2], 11, 2, 0, 200)
+    exact = np.sum(np.abs(2 * x * (x - 0.5) / 0.04), axis=1)
+    assert np.allclose(kap, exact, rtol=1e-6, atol=1e-9)
+
+    params = [13000.0, 91.19, 2.5, 20.0]
+    grid = W.random_grid(np.random.default_rng(4), 4, 100)
+    n = 3000
+    x, _, jac = orc.points(grid, 5, 1, 2**32 - 1500, n)
+    w_ref = orc.weights(grid, W.F_LO_TOY, params, 5, 1, 2**32 - 1500, n)
+    kap = T.event_kappa(orc, grid, W.F_LO_TOY, params, 5, 1, 2**32 - 1500, n)
+    moved = x * (1.0 + rng.uniform(-4, 4, size=x.shape) * T.U)
+    w_alt = np.array([orc.integrand(W.F_LO_TOY, moved[i], params) for i in range(n)]) * jac
+    assert T.weights_close(w_alt, w_ref, kap), T.weights_excess(w_alt, w_ref, kap)
+    assert kap.max() > 1e3  # points within about 1e-3 of x = 1 occur

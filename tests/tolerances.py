@@ -13,6 +13,15 @@ that an EPS-relative error of their inputs propagates to:
   delta = C_nb/nb): with every compressed weight r_i and running sum C_i
   within EPS, |d e_j| <= EPS (|e_j| + 2 (j delta + C_k) Delta_k / r_k) (the
   subtraction j delta - C_k and the division by a small r_k amplify);
+- a per-event weight w = f(x) J: the GPU's point and the oracle's point each
+  lie within two roundings of the exact point (the oracle forms e_k + frac
+  Delta_k, the GPU one fma of the remainder with Delta_k 2^-32 onto
+  e_k + 2^-33 Delta_k), so they differ by at most 4 u |x_d| per coordinate
+  (u = 2^-53), and J is the same product of the same factors in the same
+  order; the weights then differ by at most EPS (the integrand's own
+  evaluation) plus 4 u kappa(x), kappa = sum_d |x_d d ln f / d x_d| the
+  integrand's relative condition number at the point (large where f falls
+  steeply to zero, such as the LO toy's (1 - x)^3 factor at x near 1);
 - the inverse-variance combination I = sum(I_t/sigma_t^2)/sum(1/sigma_t^2):
   |dI| <= max_t |dI_t| + max_t(2 |d sigma_t|/sigma_t) max_t |I_t - I|, and
   |d sigma|/sigma <= max_t |d sigma_t|/sigma_t.
@@ -69,12 +78,56 @@ def max_rel(a, b) -> float:
     return float(np.max(np.where(d == 0, 0.0, d / np.maximum(np.abs(b), TINY))))
 
 
-def weights_close(w, w_ref, eps: float = EPS) -> bool:
-    """Per-event weights: EPS relative for every weight in the normal binary64
-    range, EPS * TINY absolute below it (zeros must be zeros)."""
+U = 2.0 ** -53  # unit roundoff of binary64
+
+
+def weights_rtol(kappa=None, eps: float = EPS):
+    """Relative bound on a per-event weight whose integrand has relative
+    condition number kappa at the event's point (see the module docstring)."""
+    if kappa is None:
+        return eps
+    return eps + 4.0 * U * np.asarray(kappa, dtype=np.float64)
+
+
+def weights_close(w, w_ref, kappa=None, eps: float = EPS) -> bool:
+    """Per-event weights: EPS (plus 4 u kappa where the integrand's condition
+    number kappa is given) relative for every weight in the normal binary64
+    range, that times TINY absolute below it (zeros must be zeros)."""
     w = np.asarray(w, dtype=np.float64)
     w_ref = np.asarray(w_ref, dtype=np.float64)
-    return bool(np.all(np.abs(w - w_ref) <= eps * np.maximum(np.abs(w_ref), TINY)))
+    tol = weights_rtol(kappa, eps) * np.maximum(np.abs(w_ref), TINY)
+    return bool(np.all(np.abs(w - w_ref) <= tol))
+
+
+def weights_excess(w, w_ref, kappa=None, eps: float = EPS) -> float:
+    """Largest |w - w_ref| / bound (<= 1 passes), for messages."""
+    w = np.asarray(w, dtype=np.float64)
+    w_ref = np.asarray(w_ref, dtype=np.float64)
+    tol = weights_rtol(kappa, eps) * np.maximum(np.abs(w_ref), TINY)
+    return float(np.max(np.abs(w - w_ref) / tol))
+
+
+def event_kappa(orc, edges, fid, params, seed, t, first, count, h: float = 1e-7):
+    """kappa(x) = sum_d |x_d d ln f / d x_d| of the oracle's integrand at the
+    points of events first .. first+count-1, by central differences of
+    relative step h (0 where f = 0). A point within h of a cut reads a large
+    kappa, which only loosens the bound for that event."""
+    x, _, _ = orc.points(edges, seed, t, first, count)
+    kap = np.zeros(count)
+    for i in range(count):
+        f0 = orc.integrand(fid, x[i], params)
+        if f0 == 0.0 or not np.isfinite(f0):
+            continue
+        s = 0.0
+        for d in range(x.shape[1]):
+            xp = x[i].copy()
+            xm = x[i].copy()
+            xp[d] *= 1.0 + h
+            xm[d] *= 1.0 - h
+            s += abs((orc.integrand(fid, xp, params) - orc.integrand(fid, xm, params))
+                     / (2.0 * h * f0))
+        kap[i] = s
+    return kap
 
 
 def _refine_terms(edges, hist, alpha):
