@@ -247,6 +247,31 @@ int vegas_nonfinite(vegas_h h, int64_t *count);
 int vegas_dump_weights(vegas_h h, int integrand_id, uint64_t seed, uint64_t first, int64_t count,
                        double *w_out);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * iteration like vegas_iterate, without a handle and without any
+ * allocation. The grid is the caller's: edges_dev, [dim][n_bins+1] binary64
+ * in device memory (read only). The outputs go to the caller's device
+ * memory: result_dev receives 4 binary64 values (I, sigma, the count of
+ * non-finite weights, t), hist_dev (may be NULL) the iteration's w^2
+ * histogram, [dim][n_bins] binary64. t is the iteration counter of the
+ * random stream; integrand_id is a built-in VEGAS_F_* with its parameters
+ * (host, copied). The work is enqueued on `stream` (a hipStream_t; NULL is
+ * the null stream) and not waited for. No refinement (vegas_refine's
+ * arithmetic needs a handle). Every buffer between the kernels (grid
+ * records, workgroup partials, histogram copies, the counter) lives in one
+ * fixed device array of the library, VEGAS_NOALLOC_SCRATCH_BYTES per GPU,
+ * held until the process ends; each call clears what must start at zero.
+ * Calls that overlap on one GPU (other streams, other threads) race on that
+ * array and must be serialised by the caller. VEGAS_EINVAL for a shape
+ * beyond VEGAS_MAX_CELLS (the array's limit), a run-time integrand id,
+ * n_events < 2 or a NULL edges_dev/result_dev; VEGAS_EDEVICE on a HIP
+ * error. */
+#define VEGAS_NOALLOC_SCRATCH_BYTES (1 << 20)
+int vegas_iterate_noalloc(int dim, int n_bins, int prec, int integrand_id, const double *params,
+                          int n_params, const double *edges_dev, int64_t n_events, uint64_t seed,
+                          uint32_t t, double *hist_dev, double *result_dev, void *stream);
+
 /* Launch shape of the iteration kernel: at most max_blocks workgroups of
  * `threads` threads (a multiple of 64 up to 1024). 0 selects the default: of
  * the powers of two from 64 up to the largest the kernel was built for

@@ -81,6 +81,8 @@ _SIGS = {
     "vegas_server_stats": ([_vp, _c.POINTER(_i64), _c.POINTER(_i64), _c.POINTER(_i64),
                             _c.POINTER(_i64)]),
     "vegas_server_destroy": ([_vp]),
+    "vegas_iterate_noalloc": ([_c.c_int, _c.c_int, _c.c_int, _c.c_int, _pd, _c.c_int, _vp,
+                               _i64, _u64, _c.c_uint32, _vp, _vp, _vp]),
     "vegas_server_set_graph": ([_vp, _c.c_int]),
     "vegas_server_ticks": ([_vp, _c.POINTER(_i64), _c.POINTER(_i64)]),
 }
@@ -281,6 +283,21 @@ def vegas_dump_weights(h: Handle, integrand_id: int, seed: int, first: int, coun
     _check(lib().vegas_dump_weights(h, integrand_id, seed, first, count,
                                     _dptr(w) if count else None), "vegas_dump_weights")
     return w
+
+
+def vegas_iterate_noalloc(dim: int, n_bins: int, prec: int, integrand_id: int, params,
+                          edges_dev: int, n_events: int, seed: int, t: int, hist_dev: int,
+                          result_dev: int, stream: int = 0):
+    """One iteration that allocates nothing: device pointers (ints) for the
+    edges, the histogram (0: none) and the 4 result values; `stream` a raw
+    hipStream_t (torch.cuda.Stream.cuda_stream). Asynchronous."""
+    p = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
+    _check(lib().vegas_iterate_noalloc(dim, n_bins, prec, integrand_id,
+                                       _dptr(p) if p.size else None, int(p.size),
+                                       _vp(edges_dev), n_events, seed, t,
+                                       _vp(hist_dev) if hist_dev else None, _vp(result_dev),
+                                       _vp(stream) if stream else None),
+           "vegas_iterate_noalloc")
 
 
 def vegas_set_launch(h: Handle, max_blocks: int = 0, threads: int = 0):
