@@ -408,11 +408,11 @@ __device__ inline void flush_hist(const LdsLayout& L, const unsigned char* smem,
 // record as the scalar byte offset, so the address costs no vector
 // instruction. The range check (index below the table size) always passes:
 // k < nb.
-typedef uint32_t rec_u32x3 __attribute__((ext_vector_type(3)));
+typedef uint32_t rec_u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t rec_u32x4 __attribute__((ext_vector_type(4)));
-__device__ rec_u32x3 rec_buffer_load_b96(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
+__device__ rec_u32x2 rec_buffer_load_b64(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
                                          int soffset, int aux)
-    __asm("llvm.amdgcn.struct.ptr.buffer.load.v3i32");
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
 __device__ rec_u32x4 rec_buffer_load_b128(__amdgpu_buffer_rsrc_t rsrc, int index, int voffset,
                                           int soffset, int aux)
     __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
@@ -427,11 +427,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rec_rsrc(const void* rec,
 
 __device__ __forceinline__ Rec32 load_rec32(__amdgpu_buffer_rsrc_t r, uint32_t k,
                                             uint32_t soff) {
-  const rec_u32x3 v = rec_buffer_load_b96(r, (int)k, 0, (int)soff, 0);
+  const rec_u32x2 v = rec_buffer_load_b64(r, (int)k, 0, (int)soff, 0);
   Rec32 g;
   g.e = __uint_as_float(v[0]);
   g.w = __uint_as_float(v[1]);
-  g.L = __uint_as_float(v[2]);
   return g;
 }
 
@@ -516,8 +515,15 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
     return integrand_f64<FID, U>(x, Dm::kMax, D_T > 0 ? D_T : D, P) * jac;
   } else {
     float x[Dm::kMax];
-    // log2 J = sum_d log2(nb Delta_d): the records' binary64-built terms
-    float l2j = 0.f;
+    // log2 J = sum over pairs of dimensions (2i, 2i+1) of log2(nb^2 Delta_2i
+    // Delta_2i+1), and log2(nb Delta) of a last unpaired dimension: binary32
+    // products (nb^2 <= 2^18 is exact) and one hardware log2 per pair, in the
+    // normal binary32 range wherever a pair's nb^2 Delta Delta >= 2^-126
+    // (bins wider than about 1e-19 / nb), and no constant D log2(nb) whose
+    // rounding would bias every weight alike
+    const float nbf = (float)nb, nb2 = (float)(nb * nb);
+    const int Dn = D_T > 0 ? D_T : D;
+    float l2j = 0.f, pw = 1.f;
 #pragma unroll
     for (int j = 0; j < Dm::kBlocks; ++j) {
       if (Dm::on(4 * j, D)) {
@@ -535,13 +541,19 @@ __device__ __forceinline__ double event_weight(uint64_t n, uint32_t t, uint32_t 
             const float y = __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, rem, 9u));
             const Rec32 g = load_rec32(rsrc, k, (uint32_t)d * nb * (uint32_t)sizeof(Rec32));
             x[d] = fmaf(y, g.w, g.e);
-            l2j = d == 0 ? g.L : l2j + g.L;
+            if ((d & 1) == 0) {
+              pw = g.w * (d + 1 < Dn ? nb2 : nbf);
+            } else {
+              pw *= g.w;
+              l2j += __builtin_amdgcn_logf(pw);
+            }
             hist[d] = HOIST ? hb[d] + (k << cshift)
                               : ((((uint32_t)d * nb) + k) << cshift) + lane_off;
           }
         }
       }
     }
+    if (Dn & 1) l2j += __builtin_amdgcn_logf(pw);
     const F32Val v = integrand_f32<FID, U>(x, Dm::kMax, D_T > 0 ? D_T : D, P);
     // w = f * 2^(log2 J + log2 f), the power split into a binary32 mantissa
     // in [1, 2) and an integer exponent applied in binary64.

@@ -26,7 +26,6 @@ __device__ inline void wg_write_records(int nb, const double* e, Rec64* rec64, R
     Rec32 r;
     r.w = (float)delta;
     r.e = (float)(lo - (double)r.w * (double)kRec32Shift);
-    r.L = (float)log2((double)nb * delta);
     rec32[k] = r;
   }
 }

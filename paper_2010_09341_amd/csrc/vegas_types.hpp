@@ -43,24 +43,22 @@ struct IntegrandArgs {
 //         whose lower edge is small against its width, bin 0 above all).
 //         Widths below 2^-990 lose bits in w (the weight is then below
 //         that times the integrand).
-//   FP32: {e, w, L} with w = Delta rounded to binary32 (the bin's own width,
+//   FP32: {e, w} with w = Delta rounded to binary32 (the bin's own width,
 //         not the difference of its rounded edges, so that a bin narrower
 //         than the binary32 spacing at its position keeps its width), e =
 //         lo - (1 - 2^-24) w rounded to binary32 (kRec32Shift: the point at
-//         fraction (l' + 1/2) 2^-23 is e + (1 + l' 2^-23) w), and
-//         L = log2(nb Delta) computed in binary64 and rounded, the bin's
-//         term of log2 of the Jacobian (a sum of these never underflows,
-//         where a product of binary32 widths would).
+//         fraction (l' + 1/2) 2^-23 is e + (1 + l' 2^-23) w). Eight bytes:
+//         one aligned 64-bit load per dimension and event.
 constexpr double kRec64Half = 0x1p-33;
 constexpr double kRec64Scale = 0x1p-32;
 constexpr float kRec32Shift = 1.0f - 0x1p-24f;
 struct Rec64 {
   double e, w;
 };
-struct alignas(4) Rec32 {
-  float e, w, L;
+struct alignas(8) Rec32 {
+  float e, w;
 };
-static_assert(sizeof(Rec32) == 12, "binary32 grid record is three words");
+static_assert(sizeof(Rec32) == 8, "binary32 grid record is two words");
 
 // LDS of the iteration kernels' workgroups: `copies` histograms of w^2
 // (binary64), interleaved per cell: the entry of cell (d, k) = d * nb + k in

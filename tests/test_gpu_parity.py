@@ -456,12 +456,15 @@ def test_narrow_bins_weights(vg, orc, dim, narrow):
     once: a Jacobian factor of (nb 1e-12)^4 from that block alone). FP64
     weights equal the oracle's at 1e-12 relative event by event. FP32-eval
     weights equal them to binary32 accuracy: the log2 of the Jacobian is a sum
-    of per-bin binary32 terms L_d = log2(nb Delta_d), each rounded once, so the
-    weight carries a relative error of at most ln2 * 2^-24 * (D + 2) *
-    (sum_d |L_d| + |log2 f|) from those roundings and the sum; each binary32
-    coordinate is off by at most 2^-23, which moves ln f of the Gaussian (width
-    a, centres 0.25) by at most 2 * 0.75 / a^2 * 2^-23 per dimension; 1e-6
-    covers the final exp2 and scaling."""
+    over pairs of dimensions of P = log2(nb^2 Delta_a Delta_b) (binary32
+    widths, each within 2^-24 relative, two binary32 products, a hardware
+    log2 within 2^-23 of |P|), so the weight carries a relative error of at
+    most 4 * 2^-24 per pair plus ln2 * 2^-24 * (pairs + 4) * (sum |P| +
+    |log2 f|) from those roundings and the sums (the pairs' nb^2 Delta Delta,
+    down to (4e-12)^2 here, stay in the normal binary32 range); each binary32
+    coordinate is off by at most 2^-23, which moves ln f of the Gaussian
+    (width a, centres 0.25) by at most 2 * 0.75 / a^2 * 2^-23 per dimension;
+    1e-6 covers the final exp2 and scaling."""
     nb = 4
     rng = np.random.default_rng(100 + dim)
     grid = _narrow_grid(rng, dim, nb, narrow)
@@ -477,9 +480,12 @@ def test_narrow_bins_weights(vg, orc, dim, narrow):
     vg.vegas_set_precision(h, W.FP32_EVAL)
     w32 = vg.vegas_dump_weights(h, W.F_GAUSS, seed, first, count)
     widths = np.diff(grid, axis=1)
-    L = np.log2(nb * widths[np.arange(dim)[None, :], k])
-    log2f = np.log2(w_ref) - np.sum(L, axis=1)
-    budget = math.log(2) * 2.0**-24 * (dim + 2) * (np.sum(np.abs(L), axis=1) + np.abs(log2f))
+    wk = widths[np.arange(dim)[None, :], k]
+    P = np.log2(nb * wk[:, 0::2]) + np.log2(nb * wk[:, 1::2])  # dim is even here
+    log2f = np.log2(w_ref) - np.sum(P, axis=1)
+    pairs = dim // 2
+    budget = 4 * 2.0**-24 * pairs + math.log(2) * 2.0**-24 * (pairs + 4) * (
+        np.sum(np.abs(P), axis=1) + np.abs(log2f))
     budget += dim * 2.0 * 0.75 / params[0] ** 2 * 2.0**-23 + 1e-6
     rel = np.abs(w32 - w_ref) / w_ref
     assert np.all(rel <= budget), np.max(rel / budget)
