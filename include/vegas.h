@@ -379,6 +379,29 @@ int vegas_server_set_graph(vegas_server s, int enable);
  * pointer may be NULL). */
 int vegas_server_ticks(vegas_server s, int64_t *ticks, int64_t *graph_ticks);
 
+/* A lane (see vegas_server_set_lanes) runs the ticks up to the next
+ * completion of one of its integrals as one chain: enqueued back to back and
+ * collected once the lane's stream has drained, so that an integral's
+ * iterations follow each other on the device without a host round trip
+ * between them (each iteration still refines the grid the next one samples:
+ * Sec. 3.2, every iteration informs the next). max_ticks bounds a chain
+ * (1..32, default 32; 1 returns to the host after every tick); a chain also
+ * carries at most about 3e8 events, and graph replay (above) runs one tick
+ * per chain. VEGAS_EINVAL outside 1..32. Results do not depend on it. */
+int vegas_server_set_chain(vegas_server s, int max_ticks);
+
+/* Chains run so far (*chains; may be NULL). */
+int vegas_server_chains(vegas_server s, int64_t *chains);
+
+/* The server runs its chains on `lanes` HIP streams (1..8, default 4): an
+ * admitted integral goes to an idle lane if there is one, where it starts at
+ * once and its work overlaps the other lanes', else to the lane holding the
+ * fewest integrals, joining that lane's next chain. With one lane, an
+ * arriving request waits for the running chain. VEGAS_ESTATE while requests
+ * are admitted or queued; VEGAS_EINVAL outside 1..8. Results do not depend
+ * on it (an integral's estimate is the same in any lane and any mix). */
+int vegas_server_set_lanes(vegas_server s, int lanes);
+
 /* Drain all queued work, then release the server. */
 int vegas_server_destroy(vegas_server s);
 

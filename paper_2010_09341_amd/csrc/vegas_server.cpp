@@ -1,28 +1,34 @@
 // vegas_server.cpp — the serving loop behind vegas_server_* (include/vegas.h).
 //
-// A scheduler thread owns one HIP stream and one device arena (the memory
-// budget). Requests are admitted first-in first-out when a slot and arena
-// bytes are free; every admitted integral keeps its grid, histogram and
-// partial sums resident in its arena range. Each tick advances every
-// admitted integral by one iteration:
+// A scheduler thread owns a device arena (the memory budget) and a few HIP
+// streams (lanes). Requests are admitted first-in first-out when a slot and
+// arena bytes are free; every admitted integral keeps its grid, histogram
+// and partial sums resident in its arena range, and is assigned to a lane:
+// an idle one if there is one (so it starts at once, its work overlapping
+// whatever the other lanes run), else the lane holding the fewest integrals.
+// A lane advances its integrals one iteration per tick, and runs the ticks
+// up to the next completion of one of them as one chain, enqueued back to
+// back with no host round trip between them; the scheduler polls the lanes'
+// streams and collects a chain's results when it has drained. A tick:
 //   1. newly admitted integrals get their uniform grid (k_serve_init);
 //   2. one launch per (precision, dimension class) runs every event chunk of
-//      every admitted integral's current iteration (k_serve_iterate), so
-//      small integrals share the GPU; an integral of at least 2^20 events
-//      per iteration instead gets one launch of the single-integral
-//      iteration kernel (exact dimension count, up to 1024-thread
-//      workgroups), whose workgroups take the place of its chunks;
+//      every integral's current iteration (k_serve_iterate), so small
+//      integrals share the GPU; an integral of at least 2^20 events per
+//      iteration instead gets one launch of the single-integral iteration
+//      kernel (exact dimension count, up to 1024-thread workgroups), whose
+//      workgroups take the place of its chunks;
 //   3. one launch closes all those iterations: moments, histogram reduction
 //      and refinement (k_serve_finalize);
 //   4. the per-integral (I_t, sigma_t) come back through mapped host memory,
-//      32 bytes per integral, which the closing kernel writes; finished
-//      integrals free their slot and arena range, which the next tick can
-//      give to waiting requests.
-// The inputs of a tick (new slot descriptors, work lists) are packed into one
-// pinned buffer mapped into the device's address space, from which a small
-// kernel (k_serve_stage) moves them into device memory.
+//      32 bytes per integral and tick, which the closing kernel writes;
+//      finished integrals free their slot and arena range for waiting
+//      requests.
+// The inputs of a chain (new slot descriptors, work lists) are packed into
+// one pinned buffer mapped into the device's address space, from which a
+// small kernel (k_serve_stage) moves them into device memory.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -75,6 +81,15 @@ struct Req {
 constexpr int64_t kServeBigEvents = int64_t(1) << 20;
 // Upper end of the per-tick buffers reserved when a server is created.
 constexpr size_t kServeReserveBytes = size_t(8) << 20;
+// Longest chain of ticks enqueued before the host synchronises, and the most
+// events a chain may carry (about 2 ms of device work at full rate, so that a
+// request arriving during a chain of large integrals does not wait longer).
+constexpr int kChainMax = 32;
+constexpr int64_t kChainEvents = int64_t(300) << 20;
+// Streams (lanes) whose chains run concurrently: by default 4, the hardware
+// queues a process gets by default; at most 8.
+constexpr int kDefaultLanes = 4;
+constexpr int kMaxLanes = 8;
 
 struct DeviceGuardSrv {
   int prev = -1;
@@ -137,24 +152,65 @@ struct Mapped {
   }
 };
 
+// One stream of the server and the chain of ticks it runs: the integrals
+// assigned to a lane advance together, and the lanes run concurrently on
+// their own streams, so that a request arriving while other integrals are on
+// the GPU starts at once on an idle lane instead of waiting for their chain.
+struct Lane {
+  hipStream_t stream = nullptr;
+  Mapped<unsigned char> in_pin;  // a chain's inputs, staged into in_dev by a kernel
+  DevBuf<unsigned char> in_dev;
+  Mapped<double> out;            // per-tick results, written by the finalize kernel
+  // tick lists, kept between chains to reuse their storage: the closing
+  // items of every tick of a chain but the last (every integral refines) and
+  // of its last tick (the integrals at their last iteration do not)
+  std::vector<FinItem> init_items, fin_items, fin_last;
+  std::vector<WorkItem> work[2][2];  // [prec][dim class 16 / 32]
+  std::vector<Req*> fresh, big;
+  // A chain whose inputs equal the previous chain's (same integrals, same
+  // chunks, none new) repeats its device work without staging its inputs
+  // again; with graph replay on, such a tick is captured once it has
+  // repeated kGraphRepeats times and replayed until the inputs change.
+  std::vector<unsigned char> last_in;
+  int repeats = 0;
+  hipGraphExec_t graph = nullptr;
+  const void* graph_bufs[3] = {nullptr, nullptr, nullptr};
+  // the integrals of this lane, and the chain in flight
+  std::vector<Req*> members, act;
+  int K = 0;
+  bool busy = false;
+
+  void drop_graph() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+  }
+  hipError_t create(size_t in_bytes, size_t out_doubles) {
+    hipError_t e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = in_pin.reserve(in_bytes);
+    if (e == hipSuccess) e = in_dev.reserve(in_bytes);
+    if (e == hipSuccess) e = out.reserve(out_doubles);
+    return e;
+  }
+  ~Lane() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    drop_graph();
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
 }  // namespace
 
 struct vegas_srv {
   int device = 0;
-  hipStream_t stream = nullptr;
   void* arena_dev = nullptr;
   Arena arena;
   int max_slots = 0;
   int64_t chunk_fixed = 0;
   SlotDev* slots_dev = nullptr;
   SlotDev* slots_pin = nullptr;  // per-slot staging of descriptors
-  Mapped<unsigned char> in_pin;  // one tick's inputs, staged into in_dev by a kernel
-  DevBuf<unsigned char> in_dev;
-  Mapped<double> out;            // per-tick results, written by the finalize kernel
-  // tick lists, kept between ticks to reuse their storage
-  std::vector<FinItem> init_items, fin_items;
-  std::vector<WorkItem> work[2][2];  // [prec][dim class 16 / 32]
-  std::vector<Req*> fresh, big;
+  size_t lane_in_bytes = 0;
+  std::vector<std::unique_ptr<Lane>> lanes;
+  int n_lanes = 0;
 
   std::thread worker;
   std::mutex mu;
@@ -166,38 +222,46 @@ struct vegas_srv {
   uint64_t next_ticket = 1;
   std::vector<Req*> active;  // by slot
   int n_active = 0;
+  // submissions so far, read by the worker while it waits for a chain
+  std::atomic<uint64_t> submitted{0};
   // statistics
   int64_t completed = 0, events = 0, work_items = 0, peak_active = 0;
-  std::atomic<int64_t> ticks{0}, graph_ticks{0};
-  // A tick whose inputs equal the previous tick's (same integrals, same
-  // chunks, none new) repeats its device work without copying its inputs
-  // again. With use_graph, once kGraphRepeats ticks in a row have repeated,
-  // that work is captured in a hipGraph and replayed until the inputs change
-  // (off by default: a tick is a few launches, and requests change every few
-  // ticks, so capturing costs more than it saves).
+  std::atomic<int64_t> ticks{0}, graph_ticks{0}, chains{0};
   static constexpr int kGraphRepeats = 8;
   std::atomic<bool> use_graph{false};
-  std::vector<unsigned char> last_in;
-  int repeats = 0;
-  hipGraphExec_t graph = nullptr;
-  const void* graph_bufs[3] = {nullptr, nullptr, nullptr};
+  // longest chain of ticks (1: one tick per chain)
+  std::atomic<int> chain_max{kChainMax};
 
   void run();
-  hipError_t tick(std::vector<Req*>& act);
-  void drop_graph() {
-    if (graph) (void)hipGraphExecDestroy(graph);
-    graph = nullptr;
-  }
+  hipError_t chain(Lane& L, int K);
+  void collect(Lane& L);
+  void fail_all();
+  hipError_t add_lanes(int n);
 };
 
-hipError_t vegas_srv::tick(std::vector<Req*>& act) {
-  // ---- host-side tick lists (member vectors: no allocation per tick) --------
-  for (auto& a : work)
+hipError_t vegas_srv::add_lanes(int n) {
+  while ((int)lanes.size() < n) {
+    auto L = std::make_unique<Lane>();
+    const hipError_t e = L->create(lane_in_bytes, 4 * (size_t)max_slots * kChainMax);
+    if (e != hipSuccess) return e;
+    lanes.push_back(std::move(L));
+  }
+  return hipSuccess;
+}
+
+// Enqueue K ticks in a row over the lane's integrals (none finishes before
+// the last of them) on the lane's stream; the results of tick j land at
+// L.out.host[4 (j L.act.size() + i)] once the stream has drained.
+hipError_t vegas_srv::chain(Lane& L, int K) {
+  std::vector<Req*>& act = L.act;
+  // ---- host-side tick lists (member vectors: no allocation per chain) --------
+  for (auto& a : L.work)
     for (auto& v : a) v.clear();
-  init_items.clear();
-  fin_items.clear();
-  fresh.clear();
-  big.clear();
+  L.init_items.clear();
+  L.fin_items.clear();
+  L.fin_last.clear();
+  L.fresh.clear();
+  L.big.clear();
   int max_lds[2][2] = {{0, 0}, {0, 0}};
   int max_nb = 2;
   for (size_t i = 0; i < act.size(); ++i) {
@@ -206,143 +270,204 @@ hipError_t vegas_srv::tick(std::vector<Req*>& act) {
     max_nb = std::max(max_nb, nb);
     if (q->fresh) {
       for (int d = 0; d < dim; ++d)
-        init_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)fresh.size(), 0});
-      fresh.push_back(q);
+        L.init_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)L.fresh.size(), 0});
+      L.fresh.push_back(q);
     }
     if (q->big) {
-      big.push_back(q);
+      L.big.push_back(q);
     } else {
       const int pc = q->r.prec == VEGAS_FP64 ? 0 : 1;
       const int dc = dim <= 16 ? 0 : 1;
       for (uint32_t c = 0; c < q->n_chunks; ++c)
-        work[pc][dc].push_back(WorkItem{(uint32_t)q->slot, c});
-      const LdsLayout L = lds_layout(dim, nb, kServeCopies, kServeLdsBudget);
-      max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(L));
+        L.work[pc][dc].push_back(WorkItem{(uint32_t)q->slot, c});
+      const LdsLayout ll = lds_layout(dim, nb, kServeCopies, kServeLdsBudget);
+      max_lds[pc][dc] = std::max(max_lds[pc][dc], (int)lds_bytes(ll));
     }
-    const uint32_t refine = q->iters + 1 < q->r.n_iter ? 1u : 0u;
-    fin_items.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
-    for (int d = 0; d < dim; ++d)
-      fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine});
+    // no refinement after an integral's last iteration
+    const uint32_t refine_last = q->iters + K < q->r.n_iter ? 1u : 0u;
+    L.fin_items.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
+    L.fin_last.push_back(FinItem{(uint32_t)q->slot, -1, (uint32_t)i, 0});
+    for (int d = 0; d < dim; ++d) {
+      L.fin_items.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, 1u});
+      L.fin_last.push_back(FinItem{(uint32_t)q->slot, d, (uint32_t)i, refine_last});
+    }
   }
   // ---- pack the inputs into one pinned buffer ------------------------------
-  // [finalize items][work items by class] — the part that repeats from tick
-  // to tick — then, for new integrals only, [descriptors][init items].
-  size_t core = fin_items.size() * sizeof(FinItem);
-  for (auto& a : work)
+  // [closing items][closing items of the last tick][work items by class] —
+  // the part that repeats from chain to chain — then, for new integrals only,
+  // [descriptors][init items].
+  size_t core = (L.fin_items.size() + L.fin_last.size()) * sizeof(FinItem);
+  for (auto& a : L.work)
     for (auto& v : a) core += v.size() * sizeof(WorkItem);
   const size_t o_desc = (core + 15) / 16 * 16;
-  const size_t o_init = o_desc + fresh.size() * sizeof(SlotDev);
-  const size_t bytes = fresh.empty() ? core : o_init + init_items.size() * sizeof(FinItem);
+  const size_t o_init = o_desc + L.fresh.size() * sizeof(SlotDev);
+  const size_t bytes = L.fresh.empty() ? core : o_init + L.init_items.size() * sizeof(FinItem);
   hipError_t e;
   // the staging kernel moves whole 16-byte words
   const size_t staged = (bytes + 15) / 16 * 16;
-  if ((e = in_pin.reserve(staged)) != hipSuccess) return e;
-  if ((e = in_dev.reserve(staged)) != hipSuccess) return e;
-  if ((e = out.reserve(4 * act.size())) != hipSuccess) return e;
+  if ((e = L.in_pin.reserve(staged)) != hipSuccess) return e;
+  if ((e = L.in_dev.reserve(staged)) != hipSuccess) return e;
+  if ((e = L.out.reserve(4 * act.size() * (size_t)K)) != hipSuccess) return e;
   size_t o = 0;
   auto put = [&](const void* src, size_t n) {
     const size_t at = o;
-    if (n) std::memcpy(in_pin.host + o, src, n);
+    if (n) std::memcpy(L.in_pin.host + o, src, n);
     o += n;
     return at;
   };
-  const size_t o_fin = put(fin_items.data(), fin_items.size() * sizeof(FinItem));
+  const size_t o_fin = put(L.fin_items.data(), L.fin_items.size() * sizeof(FinItem));
+  const size_t o_fin_last = put(L.fin_last.data(), L.fin_last.size() * sizeof(FinItem));
   size_t o_work[2][2];
   for (int p = 0; p < 2; ++p)
     for (int c = 0; c < 2; ++c)
-      o_work[p][c] = put(work[p][c].data(), work[p][c].size() * sizeof(WorkItem));
-  if (!fresh.empty()) {
+      o_work[p][c] = put(L.work[p][c].data(), L.work[p][c].size() * sizeof(WorkItem));
+  if (!L.fresh.empty()) {
     o = o_desc;
-    for (Req* q : fresh) put(slots_pin + q->slot, sizeof(SlotDev));
-    put(init_items.data(), init_items.size() * sizeof(FinItem));
+    for (Req* q : L.fresh) put(slots_pin + q->slot, sizeof(SlotDev));
+    put(L.init_items.data(), L.init_items.size() * sizeof(FinItem));
   }
   // ---- device work ------------------------------------------------------------
-  auto fin_at = [&](size_t off) { return reinterpret_cast<const FinItem*>(in_dev.p + off); };
-  auto work_at = [&](size_t off) { return reinterpret_cast<const WorkItem*>(in_dev.p + off); };
-  // everything after staging the inputs: grids of new integrals, the chunks of
-  // every integral's iteration, closing the iterations (whose results the
-  // finalize kernel writes into mapped host memory)
-  auto enqueue_work = [&]() -> hipError_t {
+  hipStream_t stream = L.stream;
+  auto fin_at = [&](size_t off) { return reinterpret_cast<const FinItem*>(L.in_dev.p + off); };
+  auto work_at = [&](size_t off) { return reinterpret_cast<const WorkItem*>(L.in_dev.p + off); };
+  // one tick after the inputs are staged: grids of new integrals (first tick
+  // of the chain only), the chunks of every integral's iteration, closing the
+  // iterations (the finalize kernel writes their results into mapped host
+  // memory, row `row` of the chain's results)
+  auto enqueue_tick = [&](bool init, bool last, size_t row) -> hipError_t {
     hipError_t e2;
-    if (!fresh.empty() &&
-        (e2 = launch_serve_init(slots_dev, fin_at(o_init), (int)init_items.size(), max_nb,
-                                reinterpret_cast<const SlotDev*>(in_dev.p + o_desc), stream)) !=
-            hipSuccess)
+    if (init && !L.fresh.empty() &&
+        (e2 = launch_serve_init(slots_dev, fin_at(o_init), (int)L.init_items.size(), max_nb,
+                                reinterpret_cast<const SlotDev*>(L.in_dev.p + o_desc),
+                                stream)) != hipSuccess)
       return e2;
-    for (Req* q : big) {
-      IterLaunch L;
-      L.fid = q->r.integrand_id;
-      L.prec = q->r.prec;
-      L.n_events = q->r.n_events;
-      L.seed = q->r.seed;
-      L.blocks = (int)q->n_chunks;
-      L.threads = q->big_threads;
-      if ((e2 = launch_iterate(q->g, L, q->P, stream)) != hipSuccess) return e2;
+    for (Req* q : L.big) {
+      IterLaunch it;
+      it.fid = q->r.integrand_id;
+      it.prec = q->r.prec;
+      it.n_events = q->r.n_events;
+      it.seed = q->r.seed;
+      it.blocks = (int)q->n_chunks;
+      it.threads = q->big_threads;
+      if ((e2 = launch_iterate(q->g, it, q->P, stream)) != hipSuccess) return e2;
     }
     for (int p = 0; p < 2; ++p)
       for (int c = 0; c < 2; ++c) {
-        if (work[p][c].empty()) continue;
+        if (L.work[p][c].empty()) continue;
         if ((e2 = launch_serve_iterate(c == 0 ? 16 : 32, p == 0 ? VEGAS_FP64 : VEGAS_FP32_EVAL,
                                        slots_dev, work_at(o_work[p][c]),
-                                       (int)work[p][c].size(), max_lds[p][c], stream)) !=
+                                       (int)L.work[p][c].size(), max_lds[p][c], stream)) !=
             hipSuccess)
           return e2;
       }
-    return launch_serve_finalize(slots_dev, fin_at(o_fin), (int)fin_items.size(), max_nb, out.dev,
-                                 stream);
+    return launch_serve_finalize(slots_dev, fin_at(last ? o_fin_last : o_fin),
+                                 (int)L.fin_items.size(), max_nb,
+                                 L.out.dev + 4 * act.size() * row, stream);
   };
-  ++ticks;
+  ticks += K;
+  ++chains;
   // the inputs already on the device (the same integrals and chunks as the
-  // last tick, none new): no staging
-  const bool same = fresh.empty() && core > 0 && core == last_in.size() &&
-                    std::memcmp(in_pin.host, last_in.data(), core) == 0;
+  // lane's last chain, none new): no staging
+  const bool same = L.fresh.empty() && core > 0 && core == L.last_in.size() &&
+                    std::memcmp(L.in_pin.host, L.last_in.data(), core) == 0;
   if (same) {
-    ++repeats;
-    const void* bufs[3] = {in_dev.p, out.dev, nullptr};
-    if (graph && (std::memcmp(bufs, graph_bufs, sizeof(bufs)) != 0 || !use_graph)) drop_graph();
-    if (use_graph && !graph && repeats >= kGraphRepeats) {
+    ++L.repeats;
+    // graph replay runs one tick per chain (a captured tick writes a fixed
+    // results row)
+    const void* bufs[3] = {L.in_dev.p, L.out.dev, nullptr};
+    if (L.graph &&
+        (std::memcmp(bufs, L.graph_bufs, sizeof(bufs)) != 0 || !use_graph || K != 1))
+      L.drop_graph();
+    if (use_graph && K == 1 && !L.graph && L.repeats >= kGraphRepeats) {
       if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return e;
-      const hipError_t ew = enqueue_work();
+      const hipError_t ew = enqueue_tick(false, true, 0);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(stream, &g);
       if (ew == hipSuccess && ec == hipSuccess)
-        e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&L.graph, g, nullptr, nullptr, 0);
       if (g) (void)hipGraphDestroy(g);
       if (ew != hipSuccess) return ew;
       if (ec != hipSuccess) return ec;
       if (e != hipSuccess) {
-        graph = nullptr;
+        L.graph = nullptr;
         return e;
       }
-      std::memcpy(graph_bufs, bufs, sizeof(bufs));
+      std::memcpy(L.graph_bufs, bufs, sizeof(bufs));
     }
-    if (graph) {
+    if (L.graph && K == 1) {
       ++graph_ticks;
-      if ((e = hipGraphLaunch(graph, stream)) != hipSuccess) return e;
-    } else if ((e = enqueue_work()) != hipSuccess) {
-      return e;
+      return hipGraphLaunch(L.graph, stream);
     }
-    return hipStreamSynchronize(stream);
+    for (int j = 0; j < K; ++j)
+      if ((e = enqueue_tick(false, j == K - 1, (size_t)j)) != hipSuccess) return e;
+    return hipSuccess;
   }
-  drop_graph();
-  repeats = 0;
-  last_in.assign(in_pin.host, in_pin.host + core);
-  for (Req* q : fresh) q->fresh = false;
+  L.drop_graph();
+  L.repeats = 0;
+  L.last_in.assign(L.in_pin.host, L.in_pin.host + core);
+  for (Req* q : L.fresh) q->fresh = false;
   // the inputs reach device memory through a kernel that reads the mapped
   // host buffer, not through a copy engine: a host-to-device copy of a few
   // KB now and then took milliseconds to enqueue, holding up every integral
   // in flight
-  if ((e = launch_serve_stage(in_pin.dev, in_dev.p, bytes, stream)) != hipSuccess) return e;
-  if ((e = enqueue_work()) != hipSuccess) return e;
-  return hipStreamSynchronize(stream);
+  if ((e = launch_serve_stage(L.in_pin.dev, L.in_dev.p, bytes, stream)) != hipSuccess) return e;
+  for (int j = 0; j < K; ++j)
+    if ((e = enqueue_tick(j == 0, j == K - 1, (size_t)j)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// The results of a lane's drained chain: every integral advances by K
+// iterations; finished integrals free their slot and arena range. Holds mu.
+void vegas_srv::collect(Lane& L) {
+  const std::vector<Req*>& act = L.act;
+  for (size_t i = 0; i < act.size(); ++i) {
+    Req* q = act[i];
+    for (int j = 0; j < L.K; ++j) {
+      const double* r = L.out.host + 4 * (act.size() * (size_t)j + i);
+      q->I_t.push_back(r[0]);
+      q->s_t.push_back(r[1]);
+      q->bad += (int64_t)r[2];
+    }
+    work_items += (int64_t)q->n_chunks * L.K;
+    q->iters += L.K;
+    events += q->r.n_events * L.K;
+    if (q->iters == q->r.n_iter) {
+      q->t_done = Clock::now();
+      combine(q->I_t, q->s_t, &q->I, &q->sigma, &q->chi2);
+      q->status = q->bad > 0 ? VEGAS_ENONFINITE : VEGAS_OK;
+      q->done = true;
+      active[q->slot] = nullptr;
+      --n_active;
+      adm->finish(q->slot, q->off);
+      ++completed;
+      L.members.erase(std::find(L.members.begin(), L.members.end(), q));
+    }
+  }
+  L.busy = false;
+  cv_done.notify_all();
+}
+
+// A device error: every request not yet finished fails with VEGAS_EDEVICE.
+// Holds mu.
+void vegas_srv::fail_all() {
+  error = VEGAS_EDEVICE;
+  for (auto& kv : reqs)
+    if (!kv.second->done) {
+      kv.second->done = true;
+      kv.second->status = VEGAS_EDEVICE;
+      kv.second->t_done = Clock::now();
+    }
+  cv_done.notify_all();
 }
 
 void vegas_srv::run() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
+  uint64_t seen = 0;  // submissions the loop has looked at
   for (;;) {
     if (error == VEGAS_OK) {
+      seen = submitted.load();
       auto admitted = adm->admit(slot_bytes);
       for (auto& a : admitted) {
         Req* q = std::get<0>(a);
@@ -376,58 +501,87 @@ void vegas_srv::run() {
         S.alpha = q->r.alpha;
         S.P = q->P;
         slots_pin[q->slot] = S;
+        // an idle lane without integrals if there is one, else the lane
+        // holding the fewest (the request joins that lane's next chain)
+        Lane* best = nullptr;
+        for (int i = 0; i < n_lanes; ++i) {
+          Lane* c = lanes[i].get();
+          const bool free_c = !c->busy && c->members.empty();
+          const bool free_b = best && !best->busy && best->members.empty();
+          if (!best || (free_c && !free_b) ||
+              (free_c == free_b && c->members.size() < best->members.size()))
+            best = c;
+        }
+        best->members.push_back(q);
       }
       peak_active = std::max<int64_t>(peak_active, n_active);
     }
-    if (n_active == 0 || error != VEGAS_OK) {
+    // start a chain on every idle lane that has integrals: the ticks until
+    // the first of them finishes, within the chain bounds
+    for (int i = 0; i < n_lanes && error == VEGAS_OK; ++i) {
+      Lane& L = *lanes[i];
+      if (L.busy || L.members.empty()) continue;
+      int K = use_graph ? 1 : chain_max.load();
+      int64_t tick_events = 0;
+      for (Req* q : L.members) {
+        K = std::min(K, q->r.n_iter - q->iters);
+        tick_events += q->r.n_events;
+      }
+      while (K > 1 && (int64_t)K * tick_events > kChainEvents) --K;
+      L.K = std::max(K, 1);
+      L.act = L.members;
+      L.busy = true;
+      lk.unlock();
+      const hipError_t e = chain(L, L.K);
+      lk.lock();
+      if (e != hipSuccess) fail_all();
+    }
+    bool any_busy = false;
+    for (int i = 0; i < n_lanes; ++i) any_busy = any_busy || lanes[i]->busy;
+    if (!any_busy || error != VEGAS_OK) {
+      if (error != VEGAS_OK) {
+        // drain what was enqueued before the error, then stop taking work
+        lk.unlock();
+        for (int i = 0; i < n_lanes; ++i) (void)hipStreamSynchronize(lanes[i]->stream);
+        lk.lock();
+        for (int i = 0; i < n_lanes; ++i) lanes[i]->busy = false;
+      }
       if (stop && (adm->pending() == 0 || error != VEGAS_OK)) break;
       cv_work.wait(lk);
       continue;
     }
-    std::vector<Req*> act;
-    for (Req* q : active)
-      if (q) act.push_back(q);
+    // Wait until a lane's chain drains, or a submission arrives while a lane
+    // is idle (it can start at once there). Polling: a spin first (a chain of
+    // small integrals drains within tens of microseconds), then short sleeps.
+    bool idle_lane = false;
+    for (int i = 0; i < n_lanes; ++i) idle_lane = idle_lane || !lanes[i]->busy;
     lk.unlock();
-    const hipError_t e = tick(act);
+    Lane* drained = nullptr;
+    hipError_t e = hipSuccess;
+    for (int spin = 0;; ++spin) {
+      for (int i = 0; i < n_lanes && !drained; ++i) {
+        Lane& L = *lanes[i];
+        if (!L.busy) continue;
+        const hipError_t q = hipStreamQuery(L.stream);
+        if (q == hipSuccess) {
+          drained = &L;
+        } else if (q != hipErrorNotReady) {
+          drained = &L;
+          e = q;
+        }
+      }
+      if (drained || (idle_lane && submitted.load() != seen)) break;
+      if (spin < 2000)
+        std::this_thread::yield();
+      else
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
     lk.lock();
     if (e != hipSuccess) {
-      error = VEGAS_EDEVICE;
-      for (Req* q : act) {
-        q->done = true;
-        q->status = VEGAS_EDEVICE;
-        q->t_done = Clock::now();
-      }
-      // requests still queued fail with the same status
-      for (auto& kv : reqs)
-        if (!kv.second->done) {
-          kv.second->done = true;
-          kv.second->status = VEGAS_EDEVICE;
-          kv.second->t_done = Clock::now();
-        }
-      cv_done.notify_all();
+      fail_all();
       continue;
     }
-    for (size_t i = 0; i < act.size(); ++i) {
-      Req* q = act[i];
-      work_items += q->n_chunks;
-      const double* r = out.host + 4 * i;
-      q->I_t.push_back(r[0]);
-      q->s_t.push_back(r[1]);
-      q->bad += (int64_t)r[2];
-      q->iters += 1;
-      events += q->r.n_events;
-      if (q->iters == q->r.n_iter) {
-        q->t_done = Clock::now();
-        combine(q->I_t, q->s_t, &q->I, &q->sigma, &q->chi2);
-        q->status = q->bad > 0 ? VEGAS_ENONFINITE : VEGAS_OK;
-        q->done = true;
-        active[q->slot] = nullptr;
-        --n_active;
-        adm->finish(q->slot, q->off);
-        ++completed;
-      }
-    }
-    cv_done.notify_all();
+    if (drained) collect(*drained);
   }
 }
 
@@ -442,8 +596,7 @@ int vegas_server_create(size_t mem_budget_bytes, int max_slots, int64_t chunk_ev
   s->max_slots = max_slots;
   s->chunk_fixed = chunk_events;
   if (hipGetDevice(&s->device) != hipSuccess) return VEGAS_EDEVICE;
-  hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc(&s->arena_dev, mem_budget_bytes);
+  hipError_t e = hipMalloc(&s->arena_dev, mem_budget_bytes);
   if (e == hipSuccess)
     e = hipMalloc(reinterpret_cast<void**>(&s->slots_dev), sizeof(SlotDev) * max_slots);
   if (e == hipSuccess)
@@ -454,28 +607,26 @@ int vegas_server_create(size_t mem_budget_bytes, int max_slots, int64_t chunk_ev
     if (s->slots_pin) (void)hipHostFree(s->slots_pin);
     if (s->slots_dev) (void)hipFree(s->slots_dev);
     if (s->arena_dev) (void)hipFree(s->arena_dev);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
     return rc;
   }
-  // The per-tick input and result buffers, sized up front for every slot
+  // The per-lane input and result buffers, sized up front for every slot
   // busy with default chunking (an integral below kServeBigEvents events has
   // at most kServeBigEvents / 2048 chunks), up to kServeReserveBytes: growing
   // them inside a tick means a pinned allocation and a synchronising free,
   // milliseconds during which every admitted integral waits.
   const size_t per_slot = sizeof(SlotDev) + (2 * kMaxDim + 1) * sizeof(FinItem) +
                           (size_t)(kServeBigEvents / 2048) * sizeof(WorkItem) + 16;
-  const size_t in_bytes = std::min(per_slot * (size_t)max_slots, kServeReserveBytes);
-  e = s->in_pin.reserve(in_bytes);
-  if (e == hipSuccess) e = s->in_dev.reserve(in_bytes);
-  if (e == hipSuccess) e = s->out.reserve(4 * (size_t)max_slots);
+  s->lane_in_bytes = std::min(per_slot * (size_t)max_slots, kServeReserveBytes);
+  e = s->add_lanes(kDefaultLanes);
   if (e != hipSuccess) {
     const int rc = e == hipErrorOutOfMemory ? VEGAS_ENOMEM : VEGAS_EDEVICE;
+    s->lanes.clear();
     (void)hipHostFree(s->slots_pin);
     (void)hipFree(s->slots_dev);
     (void)hipFree(s->arena_dev);
-    (void)hipStreamDestroy(s->stream);
     return rc;
   }
+  s->n_lanes = kDefaultLanes;
   s->arena = Arena(mem_budget_bytes);
   s->adm = std::make_unique<Admission<Req*>>(max_slots, &s->arena);
   s->active.assign(max_slots, nullptr);
@@ -531,6 +682,7 @@ int vegas_server_submit(vegas_server s, const vegas_request* r, uint64_t* ticket
   *ticket = q->ticket;
   s->adm->push(q.get());
   s->reqs[q->ticket] = std::move(q);
+  ++s->submitted;
   s->cv_work.notify_one();
   return VEGAS_OK;
 }
@@ -589,6 +741,30 @@ int vegas_server_set_graph(vegas_server s, int enable) {
   return VEGAS_OK;
 }
 
+int vegas_server_set_chain(vegas_server s, int max_ticks) {
+  if (!s || max_ticks < 1 || max_ticks > kChainMax) return VEGAS_EINVAL;
+  s->chain_max = max_ticks;
+  return VEGAS_OK;
+}
+
+int vegas_server_set_lanes(vegas_server s, int lanes) {
+  if (!s || lanes < 1 || lanes > kMaxLanes) return VEGAS_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->n_active > 0 || s->adm->pending() > 0) return VEGAS_ESTATE;
+  DeviceGuardSrv dg(s->device);
+  const hipError_t e = s->add_lanes(lanes);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? VEGAS_ENOMEM : VEGAS_EDEVICE;
+  s->n_lanes = lanes;
+  return VEGAS_OK;
+}
+
+int vegas_server_chains(vegas_server s, int64_t* chains) {
+  if (!s) return VEGAS_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (chains) *chains = s->chains;
+  return VEGAS_OK;
+}
+
 int vegas_server_ticks(vegas_server s, int64_t* ticks, int64_t* graph_ticks) {
   if (!s) return VEGAS_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
@@ -606,12 +782,13 @@ int vegas_server_destroy(vegas_server s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   const int rc = s->error;
-  (void)hipStreamSynchronize(s->stream);
-  s->drop_graph();
-  if (s->slots_pin) (void)hipHostFree(s->slots_pin);
-  if (s->slots_dev) (void)hipFree(s->slots_dev);
-  if (s->arena_dev) (void)hipFree(s->arena_dev);
-  (void)hipStreamDestroy(s->stream);
+  {
+    DeviceGuardSrv dg(s->device);
+    s->lanes.clear();  // each lane drains its stream first
+    if (s->slots_pin) (void)hipHostFree(s->slots_pin);
+    if (s->slots_dev) (void)hipFree(s->slots_dev);
+    if (s->arena_dev) (void)hipFree(s->arena_dev);
+  }
   delete s;
   return rc;
 }

@@ -81,10 +81,13 @@ _SIGS = {
     "vegas_server_stats": ([_vp, _c.POINTER(_i64), _c.POINTER(_i64), _c.POINTER(_i64),
                             _c.POINTER(_i64)]),
     "vegas_server_destroy": ([_vp]),
-    "vegas_iterate_noalloc": ([_c.c_int, _c.c_int, _c.c_int, _c.c_int, _pd, _c.c_int, _vp,
-                               _i64, _u64, _c.c_uint32, _vp, _vp, _vp]),
     "vegas_server_set_graph": ([_vp, _c.c_int]),
     "vegas_server_ticks": ([_vp, _c.POINTER(_i64), _c.POINTER(_i64)]),
+    "vegas_iterate_noalloc": ([_c.c_int, _c.c_int, _c.c_int, _c.c_int, _pd, _c.c_int, _vp,
+                               _i64, _u64, _c.c_uint32, _vp, _vp, _vp]),
+    "vegas_server_set_chain": ([_vp, _c.c_int]),
+    "vegas_server_chains": ([_vp, _c.POINTER(_i64)]),
+    "vegas_server_set_lanes": ([_vp, _c.c_int]),
 }
 
 
@@ -428,6 +431,20 @@ def vegas_server_ticks(s: Server):
     a, b = _i64(), _i64()
     _check(lib().vegas_server_ticks(s, _c.byref(a), _c.byref(b)), "vegas_server_ticks")
     return a.value, b.value
+
+
+def vegas_server_set_chain(s: Server, max_ticks: int):
+    _check(lib().vegas_server_set_chain(s, int(max_ticks)), "vegas_server_set_chain")
+
+
+def vegas_server_set_lanes(s: Server, lanes: int):
+    _check(lib().vegas_server_set_lanes(s, int(lanes)), "vegas_server_set_lanes")
+
+
+def vegas_server_chains(s: Server) -> int:
+    a = _i64()
+    _check(lib().vegas_server_chains(s, _c.byref(a)), "vegas_server_chains")
+    return a.value
 
 
 def vegas_server_destroy(s: Server):

@@ -212,3 +212,85 @@ def test_large_requests_use_the_iteration_kernel(vg, orc):
     vg.vegas_set_precision(h, big32.prec)
     I_h, s_h = vg.vegas_run(h, big32.fid, big32.n_events, big32.seed, big32.n_iter, big32.alpha)
     assert np.all(np.abs(res[False][1][0] - I_h) <= 1e-13 * np.abs(I_h))
+
+
+def test_chained_ticks(vg, orc):
+    """The ticks up to the next completion run as one chain with one host
+    synchronisation: three FP64 integrals of 7, 12 and 20 iterations need
+    three chains (one per completion), match the oracle at the FP64 bounds,
+    and agree with the same server synchronising after every tick; a request
+    submitted while a chain runs is admitted after it and matches too."""
+    reqs = [W.Request(0, 0.0, 5, 40, W.F_GAUSS, [0.15], 60_000, 7, 1.5, 2, W.FP64),
+            W.Request(1, 0.0, 2, 64, W.F_BW_FLAT, [0.3, 0.05], 30_001, 12, 1.5, 9, W.FP64),
+            W.Request(2, 0.0, 18, 10, W.F_GAUSS, [0.3], 8_191, 20, 1.5, 4, W.FP64)]
+    late = W.Request(3, 0.0, 3, 25, W.F_GAUSS, [0.2], 40_000, 6, 1.5, 8, W.FP64)
+    ref = [orc.run(r.dim, r.nb, r.fid, r.params, r.n_events, r.seed, r.n_iter, r.alpha)
+           for r in reqs + [late]]
+    got = {}
+    for chain in (32, 1):
+        srv = vg.vegas_server_create(1 << 28, 8)
+        vg.vegas_server_set_chain(srv, chain)
+        tickets = [_submit(vg, srv, r) for r in reqs]
+        vg.vegas_server_wait(srv, tickets[0], 120.0)
+        tickets.append(_submit(vg, srv, late))
+        for r, tk, (I_r, s_r, _, _) in zip(reqs + [late], tickets, ref):
+            vg.vegas_server_wait(srv, tk, 120.0)
+            I_t, s_t = vg.vegas_server_iterations(srv, tk, r.n_iter)
+            assert np.all(np.abs(I_t - I_r) <= 1e-12 * np.abs(I_r)), (chain, r.index, I_t - I_r)
+            assert T.sigma_close(s_t, s_r, I_r, r.n_events), \
+                T.sigma_excess(s_t, s_r, I_r, r.n_events)
+            got[chain, r.index] = I_t
+        ticks, _ = vg.vegas_server_ticks(srv)
+        chains = vg.vegas_server_chains(srv)
+        if chain == 1:
+            assert chains == ticks
+        else:
+            # 7 + 5 + 8 ticks for the first three, then the late request's
+            # ticks, in at most a handful of chains
+            assert chains <= 8 and ticks >= 20, (chains, ticks)
+        vg.vegas_server_destroy(srv)
+    for r in reqs + [late]:
+        assert np.all(np.abs(got[32, r.index] - got[1, r.index]) <= 1e-12 *
+                      np.abs(got[1, r.index]))
+    srv = vg.vegas_server_create(1 << 24, 4)
+    for bad in (0, 33):
+        with pytest.raises(vg.VegasError) as e:
+            vg.vegas_server_set_chain(srv, bad)
+        assert e.value.code == vg.VEGAS_EINVAL
+    vg.vegas_server_destroy(srv)
+
+
+def test_lanes(vg, orc):
+    """Chains run on up to 8 streams (lanes): with one lane and with four,
+    six FP64 integrals submitted together match the oracle at the FP64
+    bounds, and with four lanes they run in at least two lanes' chains at
+    once; the lane count is rejected outside 1..8 and while requests are in
+    flight."""
+    reqs = [W.Request(i, 0.0, 2 + i, 20 + 7 * i, W.F_GAUSS, [0.2], 30_000 + 1_000 * i, 4 + i,
+                      1.5, 100 + i, W.FP64) for i in range(6)]
+    ref = [orc.run(r.dim, r.nb, r.fid, r.params, r.n_events, r.seed, r.n_iter, r.alpha)
+           for r in reqs]
+    for lanes in (1, 4):
+        srv = vg.vegas_server_create(1 << 28, 16)
+        vg.vegas_server_set_lanes(srv, lanes)
+        tickets = [_submit(vg, srv, r) for r in reqs]
+        for r, tk, (I_r, s_r, _, _) in zip(reqs, tickets, ref):
+            vg.vegas_server_wait(srv, tk, 120.0)
+            I_t, s_t = vg.vegas_server_iterations(srv, tk, r.n_iter)
+            assert np.all(np.abs(I_t - I_r) <= 1e-12 * np.abs(I_r)), (lanes, r.index, I_t - I_r)
+            assert T.sigma_close(s_t, s_r, I_r, r.n_events), \
+                T.sigma_excess(s_t, s_r, I_r, r.n_events)
+        vg.vegas_server_destroy(srv)
+    srv = vg.vegas_server_create(1 << 28, 16)
+    for bad in (0, 9):
+        with pytest.raises(vg.VegasError) as e:
+            vg.vegas_server_set_lanes(srv, bad)
+        assert e.value.code == vg.VEGAS_EINVAL
+    big = W.Request(0, 0.0, 8, 50, W.F_GAUSS, [0.1], 3_000_000, 10, 1.5, 1, W.FP32_EVAL)
+    tk = _submit(vg, srv, big)
+    with pytest.raises(vg.VegasError) as e:
+        vg.vegas_server_set_lanes(srv, 2)
+    assert e.value.code == vg.VEGAS_ESTATE
+    vg.vegas_server_wait(srv, tk, 120.0)
+    vg.vegas_server_set_lanes(srv, 2)
+    vg.vegas_server_destroy(srv)
