@@ -38,11 +38,14 @@ def log(msg):
 
 
 def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
-    """VALU lane-instructions of one event of the Gaussian integrand: the
-    minimal gfx950 instruction sequence of the method, counted operation by
-    operation (issued instructions are measured separately with
-    SQ_INSTS_VALU; the difference is loop and compiler overhead).
+    """VALU lane-instructions of one event: the minimal gfx950 instruction
+    sequence of the method, counted operation by operation, one issue slot
+    per instruction (issued instructions are measured separately with
+    SQ_INSTS_VALU; the difference is loop and compiler overhead). Counted
+    for the Gaussian in both precisions and for the LO toy and RAMBO 2->4 in
+    FP32-eval (their configured precision); None otherwise.
 
+    Common to every integrand:
       Philox4x32-10 per 4 dimensions: 10 rounds x (2 v_mad_u64_u32 + 2
         three-input xor v_bitop3) = 40, less round 1's product of the
         workgroup-uniform counter word t (scalar unit) = 39 for the first
@@ -50,32 +53,56 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
         event index and the part of round 2 that does not depend on the
         block number: 35 each
       event index and loop: 64-bit add (1) + compare (1) = 2
-      map per dimension: 32x32->64 product giving bin and remainder (1),
-        the factor 1 + remainder 2^-32 (FP64: alignbit + shift; FP32:
-        alignbit, 23 bits) built from the remainder's bits, the grid record
-        holding the bin's origin shifted to match (2 or 1), LDS histogram
-        address (1; the grid record is read with the bin as a buffer index),
-        x = fma (1), Jacobian product (1) = 6 (FP64) or 5 (FP32), one
-        product fewer per 4-dimension block (FP32) or per event (FP64); FP32
-        also max + log2 + add per 4-dimension block (3)
-      Gaussian per dimension: subtract + fma = 2
-      weight: FP32 log2 split (add, fma, floor, subtract, exp2, two
-        converts, ldexp) = 8; FP64 exp (lower clamp, Cody-Waite reduction:
-        product, rounding and two fmas; degree-13 Taylor polynomial by
-        Horner's rule: 13 fmas; convert and ldexp = 19) + the fma forming
-        its argument and the Jacobian product (2) = 21
+      map per dimension: 32x32->64 product giving bin and remainder (1), LDS
+        histogram address (1; the grid record is read with the bin as a
+        buffer index) = 2, then
+        FP64: remainder converted (1), x = fma (1), Jacobian factor nb Delta
+          and product (2), the product of the first dimension folded = 4 per
+          dimension - 1
+        FP32: the factor 1 + remainder 2^-23 from the remainder's bits
+          (alignbit, 1), x = fma (1) = 2 per dimension; log2 J per pair of
+          dimensions: the product of their widths (1), its scaling by nb^2
+          (1), log2 (1) and the sum (1) = 4 per pair, the first sum folded;
+          an unpaired last dimension: scaling by nb, log2 and sum (3)
       non-finite check (class, two selects, count select + add) = 5;
       moments (w^2, two adds) = 3
+      FP32 weight: w = f 2^(log2 J + log2 f) with a binary64 exponent:
+        floor, subtract, exp2, two converts, ldexp = 6, plus the binary64
+        product by f and its conversion (2) where f is not a constant 1
+    Gaussian: per dimension subtract + fma = 2; FP32 log2 f = fma (1) and
+      its add to log2 J (1); FP64 exp of the sum (lower clamp, Cody-Waite
+      reduction: product, rounding and two fmas; degree-13 Taylor polynomial
+      by Horner's rule: 13 fmas; convert and ldexp = 19) + the fma forming
+      its argument (1) and the product by J (1) = 21
+    LO toy (FP32): c = fma (1); s^ = x1 x2 S (2); 1 - x1, 1 - x2 (2); their
+      cubes (4) and product (1); rsqrt of x1 x2 and its product (2);
+      s^ - m^2 (1); (dm^2 + (m G)^2) s^ (2); 1 + c^2 (1), reciprocal (1) and
+      three products (3); cut compare and select (2) = 22
+    RAMBO 2->4 (FP32), per particle: cos theta = min(fma, 1) (2); sin theta
+      = sqrt(max(fma, 0)) (3); sin, cos (2); energy -ln(u u') = max(-log2 x
+      ln 2, 0) with the product (4); three momentum components (3); then
+      the four sums of the four particles (12); mass^2 (4), rsqrt (1), boost
+      vector (3), gamma (1), 1/(1 + gamma) (2), scale (1); per particle the
+      boost: b.q (3), a b.q (1), E (2), q0 + a b.q (1), three components
+      (6); the four cyclic invariants (dot product 4, doubling 1, cut
+      compare 1 each; three products); the weight W / prod (reciprocal,
+      product, select: 3) = 166
     """
-    if fid != 2:
-        return None  # counted for the Gaussian workloads only
     blocks = (dim + 3) // 4
-    n = 39 + 35 * (blocks - 1) + 2 + 8 * dim + 5 + 3
+    common = 39 + 35 * (blocks - 1) + 2 + 2 * dim + 5 + 3
     if prec == 1:
-        n += -dim - blocks + 3 * blocks + 8
+        common += 2 * dim + 4 * (dim // 2) - 1 + 3 * (dim % 2)
     else:
-        n += -1 + 21
-    return n
+        common += 4 * dim - 1
+    if fid == 2:
+        return common + 2 * dim + (2 + 6 if prec == 1 else 21)
+    if prec != 1:
+        return None
+    if fid == 3 and dim == 4:
+        return common + 22 + 6 + 2
+    if fid == 4 and dim == 16:
+        return common + 166 + 6 + 2
+    return None
 
 
 def fp32_flops_per_event(dim: int) -> float:
@@ -84,6 +111,9 @@ def fp32_flops_per_event(dim: int) -> float:
     dimension, and the weight's fma, subtract, exp2 (4)."""
     return dim * 6 + 4
 
+
+# The configured throughput workloads measured by a default run.
+CONFIG_WORKLOADS = ("gauss8d", "lo_toy", "rambo24")
 
 KERNEL_SOURCES = ("vegas_math.hpp", "vegas_device.hpp", "vegas_iterate.hpp", "vegas_types.hpp", "iter_gauss.hip")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_iterate_gauss8d_fp32eval.md")
@@ -118,55 +148,12 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="gauss8d")
-    ap.add_argument("--latency-reps", type=int, default=1000)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the events_limit sweep, the run-time integrand and the small-workload "
-                         "latency (so a kernel trace sees only the timed launches)")
-    ap.add_argument("--serving-requests", type=int, default=1000)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 256 MiB device copy three times, so that a "
-                         "counter run can scale FETCH_SIZE/WRITE_SIZE by a known size")
-    args = ap.parse_args()
-    from paper_2010_09341_amd import vegas as _vg
-    if not os.path.exists(_vg.LIB_PATH):  # built already unless nothing is
-        from paper_2010_09341_amd import build as _build
-        _build.build()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
+def measure(vg, W, wl, steps, warmup, latency_reps):
+    """Both precisions of one workload: whole runs replayed from the captured
+    iteration graph (throughput), the same runs launched one by one with HIP
+    events around every iteration kernel on the handle's stream (kernel
+    time), and synchronous single iterations (latency)."""
     import torch
-
-    from paper_2010_09341_amd import vegas as vg
-    from paper_2010_09341_amd import workloads as W
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    wl = W.WORKLOADS[args.workload]
-    events_per_step = wl.n_events * wl.n_iter
-    # the oracle on every host core available to the process runs first, in forked
-    # processes, before this process touches the GPU
-    cpu_all = None if args.no_cpu else cpu_baseline_all_cores(wl)
-    nblk = (wl.dim + 3) // 4
 
     def make(prec):
         h = vg.vegas_create(wl.dim, wl.nb)
@@ -181,24 +168,21 @@ def main():
 
     results = {}
     for prec in (W.FP32_EVAL, W.FP64):
-        log(f"{wl.name} prec={prec}: {args.warmup} warmup + {args.steps} timed steps")
+        log(f"{wl.name} prec={prec}: {warmup} warmup + {steps} timed steps")
         h = make(prec)
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             step(h)
         torch.cuda.synchronize()
-        # throughput: whole runs, each a replay of the captured iteration graph
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             I_t, s_t, comb = step(h)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        # kernel durations: the same steps launched one by one with HIP events
-        # around every iteration kernel on the handle's stream
         vg.vegas_timing(h, True, True)
         per_step = []  # average iteration-kernel time of each step
         k_ms = k_n = 0
         t1 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             step(h)
             ms, n = vg.vegas_timing(h, True, True)
             per_step.append(ms / max(n, 1))
@@ -208,18 +192,104 @@ def main():
         dt_eager = time.perf_counter() - t1
         vg.vegas_timing(h, False)
         # per-iteration latency: one synchronous vegas_iterate (launch, kernels,
-        # 32-byte result copy, synchronisation) on the adapted grid
+        # result in mapped host memory, synchronisation) on the adapted grid
         lat = []
-        for i in range(args.latency_reps):
+        for _ in range(latency_reps):
             a = time.perf_counter()
             vg.vegas_iterate(h, wl.fid, wl.n_events, wl.seed)
             lat.append(time.perf_counter() - a)
-        log(f"prec={prec}: {dt / args.steps * 1e3:.3f} ms/step (eager {dt_eager / args.steps * 1e3:.3f}), "
-            f"kernel {k_ms / max(k_n, 1) * 1e3:.1f} us, latency p50 {pct(lat, 50) * 1e3:.3f} ms")
+        log(f"{wl.name} prec={prec}: {dt / steps * 1e3:.3f} ms/step (eager "
+            f"{dt_eager / steps * 1e3:.3f}), kernel {k_ms / max(k_n, 1) * 1e3:.1f} us, "
+            f"latency p50 {pct(lat, 50) * 1e3:.3f} ms")
         results[prec] = dict(dt=dt, dt_eager=dt_eager, I_t=I_t, s_t=s_t, comb=comb, k_ms=k_ms,
                              k_n=k_n, lat=lat, per_step=per_step)
         del h
+    return results
 
+
+def workload_summary(W, wl, res, steps):
+    """events/s of both precisions, matched sigma, and the iteration
+    kernel's roofline fraction (algorithmic VALU count x events per launch /
+    average launch time / VALU issue peak)."""
+    r32, r64 = res[W.FP32_EVAL], res[W.FP64]
+    ev = wl.n_events * wl.n_iter * steps
+    I32, s32, _ = r32["comb"]
+    I64, s64, _ = r64["comb"]
+    out = {"events_per_iteration": wl.n_events, "iterations": wl.n_iter, "dim": wl.dim,
+           "n_bins": wl.nb}
+    for prec, key in ((W.FP32_EVAL, "fp32_eval"), (W.FP64, "fp64")):
+        r = res[prec]
+        k_s = r["k_ms"] / max(r["k_n"], 1) * 1e-3
+        slots = alg_valu_per_event(wl.dim, prec, wl.fid)
+        out[key] = {"events_per_s": ev / r["dt"], "ms_per_step": r["dt"] / steps * 1e3,
+                    "kernel_us": k_s * 1e6,
+                    "kernel_us_p10_p50_p90": [pct(r["per_step"], q) * 1e3 for q in (10, 50, 90)],
+                    "valu_per_event_algorithmic": slots,
+                    "frac": slots * wl.n_events / k_s / PEAK_VALU_SLOTS if slots else None,
+                    "latency_ms_p50_p99": [pct(r["lat"], 50) * 1e3, pct(r["lat"], 99) * 1e3],
+                    "I": r["comb"][0], "sigma": r["comb"][1]}
+    out["sigma_ratio"] = s32 / s64
+    out["matched"] = abs(s32 / s64 - 1.0) < 1e-2
+    out["fp32_minus_fp64_over_sigma"] = (I32 - I64) / s64
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="gauss8d")
+    ap.add_argument("--latency-reps", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads, the events_limit sweep, the run-time "
+                         "integrand and the small-workload latency (so a kernel trace sees only "
+                         "the timed launches of one workload)")
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy three times, so that a "
+                         "counter run can scale FETCH_SIZE/WRITE_SIZE by a known size")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2010_09341_amd import workloads as W
+    wl = W.WORKLOADS[args.workload]
+    others = [] if args.no_extras else [n for n in CONFIG_WORKLOADS if n != wl.name]
+    # The oracle on every host core runs first, in processes forked before
+    # this process imports torch or makes any HIP call (the HIP runtime is not
+    # fork-safe).
+    cpu_all = None
+    if not args.no_cpu:
+        cpu_all = {name: cpu_baseline_all_cores(W.WORKLOADS[name])
+                   for name in [wl.name] + others}
+
+    from paper_2010_09341_amd import vegas as vg
+    if not os.path.exists(vg.LIB_PATH):  # built already unless nothing is
+        from paper_2010_09341_amd import build as _build
+        _build.build()
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    events_per_step = wl.n_events * wl.n_iter
+
+    results = measure(vg, W, wl, args.steps, args.warmup, args.latency_reps)
     r32, r64 = results[W.FP32_EVAL], results[W.FP64]
     value = events_per_step * args.steps / r32["dt"]
     value64 = events_per_step * args.steps / r64["dt"]
@@ -234,6 +304,13 @@ def main():
     achieved = slots * wl.n_events / k_avg_s if slots else None
     k64_avg_s = r64["k_ms"] / max(r64["k_n"], 1) * 1e-3
     slots64 = alg_valu_per_event(wl.dim, W.FP64, wl.fid)
+
+    per_workload = {wl.name: workload_summary(W, wl, results, args.steps)}
+    for name in others:
+        o = W.WORKLOADS[name]
+        res_o = measure(vg, W, o, args.steps, min(args.warmup, 5), min(args.latency_reps, 100))
+        per_workload[name] = workload_summary(W, o, res_o, args.steps)
+        per_workload[name]["fp64_I_t"] = [float(v) for v in res_o[W.FP64]["I_t"]]
 
     out = {
         "metric": "Vegas events/sec at matched sigma (FP32-eval vs FP64) on 1 GPU; "
@@ -282,12 +359,16 @@ def main():
             "launch_us_p10_p50_p90": [pct(r32["per_step"], q) * 1e3 for q in (10, 50, 90)],
             "launches": r32["k_n"],
             "fp32_flop_frac_of_157TF": (fp32_flops_per_event(wl.dim) * wl.n_events / k_avg_s
-                                        / PEAK_FP32_FLOPS) if slots else None,
+                                        / PEAK_FP32_FLOPS) if wl.fid == W.F_GAUSS else None,
             "fp64_kernel": {"avg_launch_us": k64_avg_s * 1e6,
                             "launch_us_p10_p50_p90": [pct(r64["per_step"], q) * 1e3
                                                       for q in (10, 50, 90)],
                             "frac": (slots64 * wl.n_events / k64_avg_s / PEAK_VALU_SLOTS)
                             if slots64 else None},
+            # every configured throughput workload (8-D Gaussian, LO toy, RAMBO
+            # 2->4), both precisions, with the iteration kernel's fraction of
+            # the VALU issue peak
+            "workloads": per_workload,
         },
     }
     if not args.no_extras:
@@ -307,7 +388,19 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, r64["I_t"], r64["s_t"])
-        out["cpu_baseline"]["all_cores"] = cpu_all
+        out["cpu_baseline"]["all_cores"] = cpu_all[wl.name]
+        # bounded one-core samples and all-core rates of the other workloads
+        out["cpu_baseline"]["workloads"] = {
+            name: {"one_core": cpu_sample(W.WORKLOADS[name]), "all_cores": cpu_all[name]}
+            for name in others}
+        # the GPU's FP64 iterations of the other workloads against the oracle's
+        # whole run of the same workload (stored by tests/golden/make_golden.py)
+        for name in others:
+            ref = golden_I_t(name)
+            if ref is not None:
+                got = np.asarray(per_workload[name]["fp64_I_t"])
+                out["cpu_baseline"]["workloads"][name]["fp64_gpu_vs_oracle_max_rel_err_I_t"] = \
+                    float(np.max(np.abs(got - ref) / np.abs(ref)))
     if not args.no_serving:
         out["serving"] = serving_section(vg, W, args.serving_requests)
     print(json.dumps(out))
@@ -399,12 +492,17 @@ def small_latency(vg, W, reps):
             "p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3}
 
 
-def replay(vg, W, trace, rate, max_slots, budget=4 << 30, graph=False):
+def replay(vg, W, trace, rate, max_slots, budget=4 << 30, graph=False, chain=None,
+           chunk_events=0, lanes=None):
     """Submit the trace at `rate` requests/s (inf: all at once) to a server
     with `max_slots` slots; returns latency percentiles and throughput."""
     import threading
-    srv = vg.vegas_server_create(budget, max_slots)
+    srv = vg.vegas_server_create(budget, max_slots, chunk_events)
     vg.vegas_server_set_graph(srv, graph)
+    if chain is not None:
+        vg.vegas_server_set_chain(srv, chain)
+    if lanes is not None:
+        vg.vegas_server_set_lanes(srv, lanes)
     # warm the server's kernels outside the measurement
     warm = vg.vegas_server_submit(srv, 3, 20, W.F_GAUSS, [0.2], 10_000, 2, 1.5, 0)
     vg.vegas_server_wait(srv, warm)
@@ -436,23 +534,24 @@ def replay(vg, W, trace, rate, max_slots, budget=4 << 30, graph=False):
     th.join()
     done, events, items, peak = vg.vegas_server_stats(srv)
     ticks, graph_ticks = vg.vegas_server_ticks(srv)
+    chains = vg.vegas_server_chains(srv)
     vg.vegas_server_destroy(srv)
     ev = sum(r.n_events * r.n_iter for r in trace)
     return {"rate_per_s": rate if not math.isinf(rate) else "closed-loop",
             "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3,
             "mean_ms": float(np.mean(lat)) * 1e3, "events_per_s": ev / (t_end - t0),
             "makespan_s": t_end - t0, "peak_concurrent": peak, "ticks": ticks,
-            "graph_replayed_ticks": graph_ticks}
+            "chains": chains, "graph_replayed_ticks": graph_ticks}
 
 
-def replay_median(vg, W, trace, rate, max_slots, repeats):
+def replay_median(vg, W, trace, rate, max_slots, repeats, **kw):
     """replay() `repeats` times; each figure is the median over the replays
     (the peak concurrency the largest). A host-side stall of a few
     milliseconds, seen about once in twenty replays, holds up every integral
     in flight, so one replay's p99 at a high rate can jump by ~10 ms; the
     median of three is not moved by one such replay. Each replay's p99 is
     kept in p99_ms_replays."""
-    runs = [replay(vg, W, trace, rate, max_slots) for _ in range(repeats)]
+    runs = [replay(vg, W, trace, rate, max_slots, **kw) for _ in range(repeats)]
     out = dict(runs[0])
     for k in ("p50_ms", "p99_ms", "mean_ms", "events_per_s", "makespan_s"):
         out[k] = float(np.median([r[k] for r in runs]))
@@ -461,12 +560,21 @@ def replay_median(vg, W, trace, rate, max_slots, repeats):
     return out
 
 
+def best_at(rows, slo_ms):
+    ok = [r for r in rows if r["p99_ms"] <= slo_ms]
+    return max((r["events_per_s"] for r in ok), default=0.0)
+
+
 def serving_section(vg, W, n_requests):
     """The serving stream (1000 Poisson arrivals at 200/s, mixed integrals),
     batched (up to 256 integrals at once) and one integral at a time, then a
     rate sweep (each rate replayed three times, medians); the sustained
-    throughput of each mode compared under a p99 objective of twice the
-    one-at-a-time p99 at 200/s."""
+    throughput of each mode compared under a p99 objective equal to the
+    one-at-a-time p99 at 200/s, and at fixed objectives. Both modes chain the
+    ticks up to the next completion and run chains on four streams (lanes);
+    the batched server with one lane, with and without chains, is measured
+    beside them, and the chunk size is swept at 1000 requests/s (the paper's
+    events_limit, Fig. 2, for the serving loop)."""
     trace = W.serving_trace(n_requests, rate_per_s=200.0, seed=0)
     res = {"trace": f"{n_requests} requests, Poisson arrivals at 200/s, dims U{{2..12}}, bins "
                     "U{20..100}, events/iteration log-U[1e4, 1e7], 5-10 iterations, Gaussian or "
@@ -481,67 +589,132 @@ def serving_section(vg, W, n_requests):
             log(f"serving {mode} at {rate}/s")
             rows.append(replay_median(vg, W, trace, rate, slots, 1 if math.isinf(rate) else 3))
         res[mode] = rows
-    # SLO: twice the one-at-a-time p99 at the trace's own rate (200/s)
-    slo = 2.0 * res["one_at_a_time"][0]["p99_ms"]
-    best = {}
-    for mode in modes:
-        ok = [r for r in res[mode] if r["p99_ms"] <= slo]
-        best[mode] = max((r["events_per_s"] for r in ok), default=0.0)
-    # the same server with repeated ticks replayed from captured hipGraphs
-    log("serving batched at 1000/s with graph replays")
-    res["batched_graph_replays_1000_per_s"] = replay(vg, W, trace, 1000.0, 256, graph=True)
+    # the same batched server with one stream and one tick per host
+    # synchronisation (the design without lanes and chains), and with one
+    # stream and chains
+    for key, kw in (("batched_one_lane_one_tick_per_sync", dict(chain=1, lanes=1)),
+                    ("batched_one_lane", dict(lanes=1))):
+        rows = []
+        for rate in (200.0, 1000.0, 4000.0):
+            log(f"serving {key} at {rate}/s")
+            rows.append(replay_median(vg, W, trace, rate, 256, 3, **kw))
+        res[key] = rows
+    # SLO: the one-at-a-time p99 at the trace's own rate (200/s)
+    slo = res["one_at_a_time"][0]["p99_ms"]
     res["p99_slo_ms"] = slo
+    res["p99_slo_definition"] = "one-at-a-time p99 at 200 requests/s"
+    best = {mode: best_at(res[mode], slo) for mode in modes}
     res["throughput_at_slo_events_per_s"] = best
     res["batched_over_one_at_a_time_at_slo"] = (best["batched"] / best["one_at_a_time"]
                                                 if best["one_at_a_time"] > 0 else None)
     # the same comparison at fixed p99 objectives
     table = []
-    for target in (1.0, 2.0, 5.0, 10.0, 20.0):
+    for target in (0.7, 1.0, 1.5, 2.0, 5.0, 10.0):
         row = {"p99_ms": target}
         for mode in modes:
-            ok = [r for r in res[mode] if r["p99_ms"] <= target]
-            row[mode] = max((r["events_per_s"] for r in ok), default=0.0)
+            row[mode] = best_at(res[mode], target)
         row["ratio"] = row["batched"] / row["one_at_a_time"] if row["one_at_a_time"] else None
         table.append(row)
     res["throughput_at_p99_objectives"] = table
+    # the same server with repeated ticks replayed from captured hipGraphs
+    log("serving batched at 1000/s with graph replays")
+    res["batched_graph_replays_1000_per_s"] = replay(vg, W, trace, 1000.0, 256, graph=True)
+    # chunk size of the work items (default: a function of the integral's
+    # event count; fixed sizes below, each integral cut into ceil(N/chunk)
+    # work items of one 256-thread workgroup)
+    sweep = []
+    for chunk in (10_000, 100_000, 1_000_000, 10_000_000, 100_000_000):
+        log(f"serving batched at 1000/s, chunk {chunk}")
+        row = replay(vg, W, trace, 1000.0, 256, chunk_events=chunk)
+        row["chunk_events"] = chunk
+        sweep.append(row)
+    res["chunk_sweep_1000_per_s"] = sweep
     return res
 
 
-def _oracle_chunk(args):
+def _oracle_iterations(args):
+    """Whole oracle iterations (draw, map, integrand, moments, histogram) of
+    n events on the uniform grid, iteration counters t0, t0 + 1, ..., until
+    `seconds` have passed; returns (events, seconds)."""
     import oracle
-    e, fid, params, seed, first, count = args
-    w = oracle.weights(e, fid, params, seed, 0, first, count)
-    return float(np.sum(w))
+    dim, nb, fid, params, n, seed, t0, seconds, start = args
+    e = oracle.uniform_grid(dim, nb)
+    while time.time() < start:  # every process starts together
+        time.sleep(0.001)
+    t = time.perf_counter()
+    done = 0
+    while True:
+        oracle.iterate(e, fid, params, n, seed, t0 + done // n)
+        done += n
+        if time.perf_counter() - t >= seconds:
+            return done, time.perf_counter() - t
 
 
-def cpu_baseline_all_cores(wl, chunk=1 << 16, per_core=256):
-    """The oracle's per-event work (draw, map, Jacobian, integrand) for the
-    first iteration of the workload on the uniform grid, in 2^16-event chunks
-    spread over one process per core of this machine's share (at most 16)."""
-    import multiprocessing as mp
-    import oracle
-    cores = min(16, len(os.sched_getaffinity(0)))
-    e = oracle.uniform_grid(wl.dim, wl.nb)
-    n_chunks = cores * per_core
-    jobs = [(e, wl.fid, wl.params, wl.seed, i * chunk, chunk) for i in range(n_chunks)]
-    model = ""
+def cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo names it, with its family/model/stepping."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v
+            if not line.strip() and info:
                 break
     except OSError:
         pass
+    return (f"{info.get('model name', '?')} (family {info.get('cpu family', '?')}, model "
+            f"{info.get('model', '?')}, stepping {info.get('stepping', '?')})")
+
+
+def cpu_baseline_all_cores(wl, seconds=4.0):
+    """The oracle as written on every host core available to the process (at
+    most 16): one forked process per core, each running whole iterations of
+    the workload's events split over the cores (distinct iteration counters,
+    so distinct random streams) for about `seconds`. Must run before this
+    process initialises the GPU."""
+    import multiprocessing as mp
+    import oracle
+    oracle.lib()  # build before forking
+    cores = min(16, len(os.sched_getaffinity(0)))
+    n = max(wl.n_events // cores, 1 << 16)
     with mp.get_context("fork").Pool(cores) as pool:
-        pool.map(_oracle_chunk, jobs[:cores])  # start-up outside the timing
-        t0 = time.perf_counter()
-        pool.map(_oracle_chunk, jobs, chunksize=1)
-        dt = time.perf_counter() - t0
-    return {"value": n_chunks * chunk / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
-            "cpu": model,
-            "sample": f"per-event weights (draw, map, Jacobian, integrand) of events 0..{n_chunks * chunk - 1} "
-                      f"of the {wl.name} random stream at iteration 0 on the uniform grid, "
-                      f"{n_chunks} chunks of {chunk} over {cores} processes, {dt:.1f} s"}
+        start = time.time() + 0.5
+        jobs = [(wl.dim, wl.nb, wl.fid, wl.params, n, wl.seed, 1000 * i, seconds, start)
+                for i in range(cores)]
+        res = pool.map(_oracle_iterations, jobs, chunksize=1)
+    events = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    return {"value": events / wall, "unit": "events/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"whole oracle iterations (draw, map, integrand, moments, histogram) of "
+                      f"{n} events of {wl.name} on the uniform grid, one forked process per "
+                      f"core, {events} events in {wall:.1f} s"}
+
+
+def golden_I_t(name):
+    """The oracle's per-iteration estimates of a whole run of the workload, as
+    stored under tests/golden/, or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_fp64_seed0.json")
+    try:
+        with open(path) as f:
+            return np.array([float(v) for v in json.load(f)["I_t"]])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_sample(wl, max_events=2_000_000):
+    """The oracle on one core: one whole iteration of at most `max_events`
+    events of the workload on the uniform grid (a few seconds)."""
+    import oracle
+    n = min(wl.n_events, max_events)
+    e = oracle.uniform_grid(wl.dim, wl.nb)
+    t0 = time.perf_counter()
+    oracle.iterate(e, wl.fid, wl.params, n, wl.seed, 0)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"one iteration of {n} events of {wl.name} (FP64, seed {wl.seed}, "
+                      f"uniform grid), {dt:.1f} s"}
 
 
 def gpu_share(vg, W, wl, steps):
@@ -575,6 +748,7 @@ def cpu_baseline(wl, gpu_I_t, gpu_s_t):
                                 wl.alpha)
     dt = time.perf_counter() - t0
     res = {"value": n_ev * n_iter / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+           "cpu": cpu_model(),
            "sample": f"first {n_iter} of {wl.n_iter} iterations of {wl.name} at "
                      f"{n_ev:.0e} events each (FP64, seed {wl.seed}), {dt:.1f} s"}
     if n_ev == wl.n_events:
