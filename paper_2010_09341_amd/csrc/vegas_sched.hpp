@@ -121,15 +121,19 @@ class Admission {
   std::vector<int> free_slots_;
 };
 
-// Events per chunk for an integral of n events per iteration: about n/2048
-// (so that a large integral alone still gives every CU several workgroups),
-// a multiple of 256, between 2048 (so that a small integral still spreads
-// over several workgroups) and 262144 (or `fixed` when non-zero).
+// Events per chunk for an integral of n events per iteration: about n/512,
+// a multiple of 256 (one event per thread of a 256-thread workgroup), between
+// 256 and 262144 (or `fixed` when non-zero). A chunk is one workgroup, which
+// holds one wave per SIMD, so its events run latency-bound: small chunks
+// spread an integral over more CUs and shorten its iteration. Measured on
+// the serving trace at 200 requests/s, median latency of integrals below
+// 1e5 events: 0.199 ms with chunks of at least 2048 events, 0.131 ms with
+// 256; from 1e5 to 1e6 events: 0.222 and 0.171 ms (512).
 inline int64_t chunk_events(int64_t n, int64_t fixed) {
   if (fixed > 0) return fixed;
-  int64_t c = (n + 2047) / 2048;
+  int64_t c = (n + 511) / 512;
   c = (c + 255) / 256 * 256;
-  return std::min<int64_t>(std::max<int64_t>(c, 2048), 262144);
+  return std::min<int64_t>(std::max<int64_t>(c, 256), 262144);
 }
 
 }  // namespace vegas

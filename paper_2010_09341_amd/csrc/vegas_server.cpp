@@ -79,8 +79,8 @@ struct Req {
 // Requests of at least this many events per iteration run as single-integral
 // iteration-kernel launches rather than as chunks of the batched kernel.
 constexpr int64_t kServeBigEvents = int64_t(1) << 20;
-// Upper end of the per-tick buffers reserved when a server is created.
-constexpr size_t kServeReserveBytes = size_t(8) << 20;
+// Upper end of each lane's input buffers reserved when a server is created.
+constexpr size_t kServeReserveBytes = size_t(4) << 20;
 // Longest chain of ticks enqueued before the host synchronises, and the most
 // events a chain may carry (about 2 ms of device work at full rate, so that a
 // request arriving during a chain of large integrals does not wait longer).
@@ -611,11 +611,12 @@ int vegas_server_create(size_t mem_budget_bytes, int max_slots, int64_t chunk_ev
   }
   // The per-lane input and result buffers, sized up front for every slot
   // busy with default chunking (an integral below kServeBigEvents events has
-  // at most kServeBigEvents / 2048 chunks), up to kServeReserveBytes: growing
-  // them inside a tick means a pinned allocation and a synchronising free,
-  // milliseconds during which every admitted integral waits.
-  const size_t per_slot = sizeof(SlotDev) + (2 * kMaxDim + 1) * sizeof(FinItem) +
-                          (size_t)(kServeBigEvents / 2048) * sizeof(WorkItem) + 16;
+  // at most kServeBigEvents / 512 chunks, and a chain two lists of closing
+  // items), up to kServeReserveBytes: growing them inside a chain means a
+  // pinned allocation and a synchronising free, milliseconds during which
+  // every integral of the lane waits.
+  const size_t per_slot = sizeof(SlotDev) + 2 * (kMaxDim + 1) * sizeof(FinItem) +
+                          (size_t)(kServeBigEvents / 512) * sizeof(WorkItem) + 16;
   s->lane_in_bytes = std::min(per_slot * (size_t)max_slots, kServeReserveBytes);
   e = s->add_lanes(kDefaultLanes);
   if (e != hipSuccess) {

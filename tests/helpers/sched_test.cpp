@@ -85,13 +85,14 @@ static void admission() {
 }
 
 static void chunks() {
-  CHECK(vegas::chunk_events(10000, 0) == 2048);
-  CHECK(vegas::chunk_events(10000000, 0) == 5120);
+  CHECK(vegas::chunk_events(10000, 0) == 256);
+  CHECK(vegas::chunk_events(300000, 0) == 768);
+  CHECK(vegas::chunk_events(10000000, 0) == 19712);
   CHECK(vegas::chunk_events(100000000000LL, 0) == 262144);
   CHECK(vegas::chunk_events(123, 777) == 777);
   for (long long n : {2LL, 4097LL, 1000003LL, 123456789LL}) {
     const long long c = vegas::chunk_events(n, 0);
-    CHECK(c % 256 == 0 && c >= 2048 && c <= 262144);
+    CHECK(c % 256 == 0 && c >= 256 && c <= 262144);
   }
 }
 
