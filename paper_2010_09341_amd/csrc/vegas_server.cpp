@@ -441,7 +441,8 @@ void vegas_srv::collect(Lane& L) {
       --n_active;
       adm->finish(q->slot, q->off);
       ++completed;
-      L.members.erase(std::find(L.members.begin(), L.members.end(), q));
+      const auto it = std::find(L.members.begin(), L.members.end(), q);
+      if (it != L.members.end()) L.members.erase(it);
     }
   }
   L.busy = false;
@@ -551,14 +552,16 @@ void vegas_srv::run() {
       continue;
     }
     // Wait until a lane's chain drains, or a submission arrives while a lane
-    // is idle (it can start at once there). Polling: a spin first (a chain of
-    // small integrals drains within tens of microseconds), then short sleeps.
+    // is idle (it can start at once there). Polling: a spin for the first
+    // millisecond (a chain of small integrals drains within a few hundred
+    // microseconds), then 20-microsecond sleeps.
     bool idle_lane = false;
     for (int i = 0; i < n_lanes; ++i) idle_lane = idle_lane || !lanes[i]->busy;
     lk.unlock();
     Lane* drained = nullptr;
     hipError_t e = hipSuccess;
-    for (int spin = 0;; ++spin) {
+    const auto spin_until = Clock::now() + std::chrono::milliseconds(1);
+    for (;;) {
       for (int i = 0; i < n_lanes && !drained; ++i) {
         Lane& L = *lanes[i];
         if (!L.busy) continue;
@@ -571,7 +574,7 @@ void vegas_srv::run() {
         }
       }
       if (drained || (idle_lane && submitted.load() != seen)) break;
-      if (spin < 2000)
+      if (Clock::now() < spin_until)
         std::this_thread::yield();
       else
         std::this_thread::sleep_for(std::chrono::microseconds(20));
