@@ -6,6 +6,8 @@
 //   chunk_events  the event-chunk size of an integral (a function of its
 //               event count only, so an integral is cut the same way alone
 //               and in a mix)
+//   pick_lane   the stream (lane) a newly admitted integral joins
+//   chain_ticks how many ticks a lane runs before returning to the host
 #pragma once
 
 #include <stddef.h>
@@ -134,6 +136,36 @@ inline int64_t chunk_events(int64_t n, int64_t fixed) {
   int64_t c = (n + 511) / 512;
   c = (c + 255) / 256 * 256;
   return std::min<int64_t>(std::max<int64_t>(c, 256), 262144);
+}
+
+// The lane a newly admitted integral joins, of n lanes with busy[i] (a chain
+// in flight) and members[i] (integrals assigned): the first idle lane
+// without integrals, where it starts at once; else the lane holding the
+// fewest integrals (the first of equals), whose next chain it joins.
+inline int pick_lane(int n, const bool* busy, const size_t* members) {
+  int best = 0;
+  for (int i = 1; i < n; ++i) {
+    const bool free_i = !busy[i] && members[i] == 0;
+    const bool free_b = !busy[best] && members[best] == 0;
+    if ((free_i && !free_b) || (free_i == free_b && members[i] < members[best])) best = i;
+  }
+  return best;
+}
+
+// Ticks of a lane's next chain: up to the first completion among its
+// integrals (remaining[i] iterations left, events[i] per iteration), at most
+// max_ticks, and at most max_events events in all unless one tick alone
+// carries more; at least 1.
+inline int chain_ticks(int n, const int* remaining, const int64_t* events, int max_ticks,
+                       int64_t max_events) {
+  int K = max_ticks;
+  int64_t tick_events = 0;
+  for (int i = 0; i < n; ++i) {
+    K = std::min(K, remaining[i]);
+    tick_events += events[i];
+  }
+  while (K > 1 && (int64_t)K * tick_events > max_events) --K;
+  return std::max(K, 1);
 }
 
 }  // namespace vegas

@@ -502,18 +502,13 @@ void vegas_srv::run() {
         S.alpha = q->r.alpha;
         S.P = q->P;
         slots_pin[q->slot] = S;
-        // an idle lane without integrals if there is one, else the lane
-        // holding the fewest (the request joins that lane's next chain)
-        Lane* best = nullptr;
+        bool busy[kMaxLanes];
+        size_t members[kMaxLanes];
         for (int i = 0; i < n_lanes; ++i) {
-          Lane* c = lanes[i].get();
-          const bool free_c = !c->busy && c->members.empty();
-          const bool free_b = best && !best->busy && best->members.empty();
-          if (!best || (free_c && !free_b) ||
-              (free_c == free_b && c->members.size() < best->members.size()))
-            best = c;
+          busy[i] = lanes[i]->busy;
+          members[i] = lanes[i]->members.size();
         }
-        best->members.push_back(q);
+        lanes[pick_lane(n_lanes, busy, members)]->members.push_back(q);
       }
       peak_active = std::max<int64_t>(peak_active, n_active);
     }
@@ -522,14 +517,14 @@ void vegas_srv::run() {
     for (int i = 0; i < n_lanes && error == VEGAS_OK; ++i) {
       Lane& L = *lanes[i];
       if (L.busy || L.members.empty()) continue;
-      int K = use_graph ? 1 : chain_max.load();
-      int64_t tick_events = 0;
-      for (Req* q : L.members) {
-        K = std::min(K, q->r.n_iter - q->iters);
-        tick_events += q->r.n_events;
+      std::vector<int> remaining(L.members.size());
+      std::vector<int64_t> ev(L.members.size());
+      for (size_t m = 0; m < L.members.size(); ++m) {
+        remaining[m] = L.members[m]->r.n_iter - L.members[m]->iters;
+        ev[m] = L.members[m]->r.n_events;
       }
-      while (K > 1 && (int64_t)K * tick_events > kChainEvents) --K;
-      L.K = std::max(K, 1);
+      L.K = chain_ticks((int)L.members.size(), remaining.data(), ev.data(),
+                        use_graph ? 1 : chain_max.load(), kChainEvents);
       L.act = L.members;
       L.busy = true;
       lk.unlock();

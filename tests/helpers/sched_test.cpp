@@ -1,6 +1,6 @@
 // Test-only driver for the serving scheduler's host logic (no GPU): the
-// device-arena allocator, FIFO admission by slot and memory, and the
-// event-chunk rule. Prints "ok" and exits 0 on success.
+// device-arena allocator, FIFO admission by slot and memory, the event-chunk
+// rule, the choice of lane and the length of a chain. Prints "ok" and exits 0 on success.
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -96,11 +96,38 @@ static void chunks() {
   }
 }
 
+static void lanes() {
+  bool busy[4] = {true, false, false, true};
+  size_t members[4] = {3, 2, 0, 0};
+  CHECK(vegas::pick_lane(4, busy, members) == 2);  // idle and empty
+  members[2] = 1;
+  CHECK(vegas::pick_lane(4, busy, members) == 3);  // none free: fewest integrals
+  busy[3] = false;
+  CHECK(vegas::pick_lane(4, busy, members) == 3);  // idle and empty again
+  bool all_busy[2] = {true, true};
+  size_t eq[2] = {1, 1};
+  CHECK(vegas::pick_lane(2, all_busy, eq) == 0);   // the first of equals
+  CHECK(vegas::pick_lane(1, all_busy, eq) == 0);
+}
+
+static void chains() {
+  const int rem[3] = {7, 5, 9};
+  const int64_t ev[3] = {1000, 2000, 3000};
+  CHECK(vegas::chain_ticks(3, rem, ev, 32, 1LL << 40) == 5);   // the first completion
+  CHECK(vegas::chain_ticks(3, rem, ev, 3, 1LL << 40) == 3);    // the tick bound
+  CHECK(vegas::chain_ticks(3, rem, ev, 32, 13000) == 2);       // 6000 events per tick
+  CHECK(vegas::chain_ticks(3, rem, ev, 32, 100) == 1);         // one tick even if larger
+  const int one[1] = {1};
+  CHECK(vegas::chain_ticks(1, one, ev, 32, 1LL << 40) == 1);
+}
+
 int main() {
   arena_basic();
   arena_random();
   admission();
   chunks();
+  lanes();
+  chains();
   std::printf("ok\n");
   return 0;
 }
