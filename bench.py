@@ -403,6 +403,12 @@ def main():
                     float(np.max(np.abs(got - ref) / np.abs(ref)))
     if not args.no_serving:
         out["serving"] = serving_section(vg, W, args.serving_requests)
+    # the paper's own timings (Table 1), context only: another machine, an
+    # integral and event count it does not state
+    out["paper_context"] = {
+        "what": "seconds per iteration on SLURM CPU nodes of 4 cores (Table 1); integrand, events "
+                "and precision not stated; not a target",
+        "nodes_1_2_3_s": [59.7, 33.3, 22.3]}
     print(json.dumps(out))
 
 
