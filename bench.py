@@ -82,11 +82,12 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
       = sqrt(max(fma, 0)) (3); sin, cos (2); energy -ln(u u') = max(-log2 x
       ln 2, 0) with the product (4); three momentum components (3); then
       the four sums of the four particles (12); mass^2 (4), rsqrt (1), boost
-      vector (3), gamma (1), 1/(1 + gamma) (2), scale (1); per particle the
-      boost: b.q (3), a b.q (1), E (2), q0 + a b.q (1), three components
-      (6); the four cyclic invariants (dot product 4, doubling 1, cut
-      compare 1 each; three products); the weight W / prod (reciprocal,
-      product, select: 3) = 166
+      vector (3), gamma (1), 1/(1 + gamma) (2), the cut on the unscaled
+      invariants, c M^2 / 2s (1); per particle the boost of the unscaled
+      momenta: b.q (3), q0 + a b.q (1), E (1), three components (3); the
+      four cyclic invariants of the unscaled momenta (dot product 4, cut
+      compare 1 each; three products); the weight (W / 16 s^4) M^8 / prod
+      (M^4, M^8, constant, reciprocal, product, select: 6) = 145
     """
     blocks = (dim + 3) // 4
     common = 39 + 35 * (blocks - 1) + 2 + 2 * dim + 5 + 3
@@ -101,7 +102,7 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
     if fid == 3 and dim == 4:
         return common + 22 + 6 + 2
     if fid == 4 and dim == 16:
-        return common + 166 + 6 + 2
+        return common + 145 + 6 + 2
     return None
 
 

@@ -246,8 +246,13 @@ struct F32Val {
 };
 
 __device__ __forceinline__ float rambo24_f32(const float* x, const IntegrandArgs& P) {
-  const float sqrt_s = P.f[0], W = P.f[1], cut = P.f[2];
+  const float W = P.f[1];
   if (P.mode == 1) return W;
+  // RAMBO's final scaling x = sqrt(s)/M is never applied: with p = x p' the
+  // invariants are s_ij = 2 x^2 (p'_i.p'_j) = (2 s / M^2) d_ij, so the cut
+  // s_ij > c reads d_ij > (c / 2s) M^2 and the weight W / prod s_ij reads
+  // (W / 16 s^4) M^8 / prod d_ij (P.f[3] = c / 2s, P.f[4] = W / 16 s^4)
+  const float cut_d = P.f[3], w_d = P.f[4];
   float q[4][4];
   float Q0 = 0.f, Qx = 0.f, Qy = 0.f, Qz = 0.f;
 #pragma unroll
@@ -275,28 +280,29 @@ __device__ __forceinline__ float rambo24_f32(const float* x, const IntegrandArgs
   const float bx = -Qx * iM, by = -Qy * iM, bz = -Qz * iM;
   const float gam = Q0 * iM;
   const float a = __builtin_amdgcn_rcpf(1.f + gam);
-  const float xs = sqrt_s * iM;
+  // the boosted momenta before the scaling
   float p[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const float bq = bx * q[i][1] + by * q[i][2] + bz * q[i][3];
-    const float abq = a * bq;
-    p[i][0] = xs * (gam * q[i][0] + bq);
-    p[i][1] = xs * (q[i][1] + bx * (q[i][0] + abq));
-    p[i][2] = xs * (q[i][2] + by * (q[i][0] + abq));
-    p[i][3] = xs * (q[i][3] + bz * (q[i][0] + abq));
+    const float e = q[i][0] + a * bq;
+    p[i][0] = gam * q[i][0] + bq;
+    p[i][1] = q[i][1] + bx * e;
+    p[i][2] = q[i][2] + by * e;
+    p[i][3] = q[i][3] + bz * e;
   }
+  const float thr = cut_d * M2;
   float prod = 1.f;
   bool pass = true;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int j = (i + 1) & 3;
-    const float sij =
-        2.f * (p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3]);
-    pass = pass && (sij > cut);
-    prod *= sij;
+    const float dij = p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3];
+    pass = pass && (dij > thr);
+    prod *= dij;
   }
-  return pass ? W * __builtin_amdgcn_rcpf(prod) : 0.f;
+  const float m4 = M2 * M2;
+  return pass ? w_d * (m4 * m4) * __builtin_amdgcn_rcpf(prod) : 0.f;
 }
 
 template <int FID, class U = NoUser>
