@@ -75,9 +75,9 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
       by Horner's rule: 13 fmas; convert and ldexp = 19) + the fma forming
       its argument (1) and the product by J (1) = 21
     LO toy (FP32): c = fma (1); s^ = x1 x2 S (2); 1 - x1, 1 - x2 (2); their
-      cubes (4) and product (1); rsqrt of x1 x2 and its product (2);
+      product and its cube (3); rsqrt of x1 x2 and its product (2);
       s^ - m^2 (1); (dm^2 + (m G)^2) s^ (2); 1 + c^2 (1), reciprocal (1) and
-      three products (3); cut compare and select (2) = 22
+      three products (3); cut compare and select (2) = 20
     RAMBO 2->4 (FP32), per particle: cos theta = min(fma, 1) (2); sin theta
       = sqrt(max(fma, 0)) (3); sin, cos (2); energy -ln(u u') = max(-log2 x
       ln 2, 0) with the product (4); three momentum components (3); then
@@ -100,7 +100,7 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
     if prec != 1:
         return None
     if fid == 3 and dim == 4:
-        return common + 22 + 6 + 2
+        return common + 20 + 6 + 2
     if fid == 4 and dim == 16:
         return common + 145 + 6 + 2
     return None

@@ -333,8 +333,9 @@ __device__ __forceinline__ F32Val integrand_f32(const float* x, int DMAX, int D,
     const float x1 = x[0], x2 = x[1];
     const float c = fmaf(2.f, x[2], -1.f);
     const float shat = x1 * x2 * S;
-    const float y1 = 1.f - x1, y2 = 1.f - x2;
-    const float g12 = (y1 * y1 * y1) * (y2 * y2 * y2) * __builtin_amdgcn_rsqf(x1 * x2);
+    // g(x1) g(x2) = ((1 - x1)(1 - x2))^3 / sqrt(x1 x2)
+    const float y12 = (1.f - x1) * (1.f - x2);
+    const float g12 = (y12 * y12 * y12) * __builtin_amdgcn_rsqf(x1 * x2);
     const float dm = shat - m2;
     const float den = fmaf(dm, dm, mG * mG) * shat;
     const float v = g12 * fmaf(c, c, 1.f) * norm * __builtin_amdgcn_rcpf(den);
