@@ -142,8 +142,12 @@ __device__ __forceinline__ double wave_scan_excl(double v) {
 // Integrands in binary64. x[0..D) in the unit hypercube.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double rambo24_f64(const double* x, const IntegrandArgs& P) {
-  const double sqrt_s = P.d[0], W = P.d[1], cut = P.d[2], two_pi = P.d[3];
+  const double W = P.d[1];
   if (P.mode == 1) return W;
+  // As in binary32, the final scaling x = sqrt(s)/M is not applied: the cut
+  // on s_ij = (2 s / M^2) d_ij reads d_ij > (c / 2s) M^2 and the weight is
+  // (W / 16 s^4) M^8 / prod d_ij (P.d[4] = c / 2s, P.d[5] = W / 16 s^4).
+  const double cut_d = P.d[4], w_d = P.d[5];
   double q[4][4];
   double Q0 = 0.0, Qx = 0.0, Qy = 0.0, Qz = 0.0;
 #pragma unroll
@@ -151,8 +155,8 @@ __device__ __forceinline__ double rambo24_f64(const double* x, const IntegrandAr
     const double ct = 2.0 * x[4 * i] - 1.0;
     const double st = sqrt(1.0 - ct * ct);
     double sp, cp;
-    sincos(two_pi * x[4 * i + 1], &sp, &cp);
-    const double en = -log(x[4 * i + 2] * x[4 * i + 3]);
+    sincos_turns_f64(x[4 * i + 1], &sp, &cp);  // sin, cos of 2 pi u
+    const double en = -log_f64(x[4 * i + 2] * x[4 * i + 3]);
     q[i][0] = en;
     q[i][1] = en * st * cp;
     q[i][2] = en * st * sp;
@@ -162,30 +166,32 @@ __device__ __forceinline__ double rambo24_f64(const double* x, const IntegrandAr
     Qy += q[i][2];
     Qz += q[i][3];
   }
-  const double M = sqrt(Q0 * Q0 - Qx * Qx - Qy * Qy - Qz * Qz);
-  const double bx = -Qx / M, by = -Qy / M, bz = -Qz / M;
-  const double gam = Q0 / M;
+  const double M2 = Q0 * Q0 - Qx * Qx - Qy * Qy - Qz * Qz;
+  const double iM = 1.0 / sqrt(M2);
+  const double bx = -Qx * iM, by = -Qy * iM, bz = -Qz * iM;
+  const double gam = Q0 * iM;
   const double a = 1.0 / (1.0 + gam);
-  const double xs = sqrt_s / M;
   double p[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const double bq = bx * q[i][1] + by * q[i][2] + bz * q[i][3];
-    p[i][0] = xs * (gam * q[i][0] + bq);
-    p[i][1] = xs * (q[i][1] + bx * q[i][0] + a * bq * bx);
-    p[i][2] = xs * (q[i][2] + by * q[i][0] + a * bq * by);
-    p[i][3] = xs * (q[i][3] + bz * q[i][0] + a * bq * bz);
+    const double e = q[i][0] + a * bq;
+    p[i][0] = gam * q[i][0] + bq;
+    p[i][1] = q[i][1] + bx * e;
+    p[i][2] = q[i][2] + by * e;
+    p[i][3] = q[i][3] + bz * e;
   }
-  double f = W;
+  const double thr = cut_d * M2;
+  double prod = 1.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int j = (i + 1) & 3;
-    const double sij =
-        2.0 * (p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3]);
-    if (!(sij > cut)) return 0.0;
-    f /= sij;
+    const double dij = p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3];
+    if (!(dij > thr)) return 0.0;
+    prod *= dij;
   }
-  return f;
+  const double m4 = M2 * M2;
+  return w_d * (m4 * m4) / prod;
 }
 
 // The integrand of a kernel compiled at run time: U::f64 / U::f32 wrap the
@@ -219,14 +225,16 @@ __device__ __forceinline__ double integrand_f64(const double* x, int DMAX, int D
     const double S = P.d[0], m2 = P.d[1], mG = P.d[2], norm = P.d[3], cut = P.d[4];
     const double x1 = x[0], x2 = x[1];
     const double c = 2.0 * x[2] - 1.0;
-    const double shat = x1 * x2 * S;
+    const double x12 = x1 * x2;
+    const double shat = x12 * S;
     if (!(sqrt(shat) > cut)) return 0.0;
-    const double y1 = 1.0 - x1, y2 = 1.0 - x2;
-    const double g1 = y1 * y1 * y1 / sqrt(x1);
-    const double g2 = y2 * y2 * y2 / sqrt(x2);
+    // g(x1) g(x2) (1 + c^2) BW / s^ with g(x) = (1 - x)^3 / sqrt(x) and
+    // BW = norm / ((s^ - m^2)^2 + (m G)^2), norm = (m G / pi) 2 2 pi: one
+    // square root and one division
+    const double y12 = (1.0 - x1) * (1.0 - x2);
     const double dm = shat - m2;
-    const double bw = norm / (dm * dm + mG * mG);  // norm = (m G / pi) * 2 * 2 pi
-    return g1 * g2 * (1.0 + c * c) * bw / shat;
+    const double num = y12 * y12 * y12 * (1.0 + c * c) * norm;
+    return num / (sqrt(x12) * (dm * dm + mG * mG) * shat);
   } else if constexpr (FID == kRambo24) {
     return rambo24_f64(x, P);
   } else {  // kBwFlat

@@ -146,13 +146,16 @@ int build_integrand_args(int fid, int dim, const double* p, int np, IntegrandArg
       a.d[1] = (pi / 2.0) * (pi / 2.0) * (pi / 2.0) * s * s / 12.0;
       a.d[2] = cut_frac * s;
       a.d[3] = 2.0 * pi;
+      // the cut and the weight on the invariants of the unscaled momenta
+      a.d[4] = a.d[2] / (2.0 * s);
+      a.d[5] = a.d[1] / (16.0 * s * s * s * s);
       a.f[0] = (float)a.d[0];
       a.f[1] = (float)a.d[1];
       a.f[2] = (float)a.d[2];
-      // the binary32 form never applies RAMBO's final scale: its cut and its
-      // weight are carried as c/(2s) and W/(16 s^4)
-      a.f[3] = (float)(a.d[2] / (2.0 * s));
-      a.f[4] = (float)(a.d[1] / (16.0 * s * s * s * s));
+      // neither form applies RAMBO's final scale: the cut and the weight are
+      // carried as c/(2s) and W/(16 s^4)
+      a.f[3] = (float)a.d[4];
+      a.f[4] = (float)a.d[5];
       a.mode = (int)mode;
       break;
     }

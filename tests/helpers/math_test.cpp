@@ -1,6 +1,7 @@
 // Host harness for the binary64 functions of vegas_math.hpp: reads lines
-// "e x", "l x" or "p x a" from stdin and prints exp_f64(x), log_f64(x) or
-// pow_pos(x, a) with 17 significant digits.
+// "e x", "l x", "p x a", "s u" or "c u" from stdin and prints exp_f64(x),
+// log_f64(x), pow_pos(x, a), or the sine or cosine of sincos_turns_f64(u)
+// with 17 significant digits.
 #include <cstdio>
 
 #include "vegas_math.hpp"
@@ -16,6 +17,10 @@ int main() {
       y = vegas::log_f64(x);
     } else if (op == 'p' && std::scanf("%lf", &a) == 1) {
       y = vegas::pow_pos(x, a);
+    } else if (op == 's' || op == 'c') {
+      double sn, cs;
+      vegas::sincos_turns_f64(x, &sn, &cs);
+      y = op == 's' ? sn : cs;
     } else {
       return 1;
     }
