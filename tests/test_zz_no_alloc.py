@@ -86,3 +86,38 @@ def test_noalloc_rejections(vg):
             vg.vegas_iterate_noalloc(dim, nb, prec, fid, None, edges.data_ptr(), n, 0, 0, 0,
                                      res.data_ptr(), 0)
         assert e.value.code == vg.VEGAS_EINVAL, (dim, nb, prec, fid, n)
+
+
+def test_noalloc_under_graph_capture(vg):
+    """The callers it is for: one iteration captured into a hipGraph by torch
+    (global capture mode, in which an allocation anywhere in the process makes
+    the capture fail), replayed three times with eager work and
+    synchronisations between the replays; every replay reproduces the eager
+    call's (I, sigma) exactly and its histogram to rounding (atomics add in no
+    fixed order)."""
+    import torch
+    dim, nb, fid, params, n, seed, t = 5, 30, W.F_GAUSS, [0.2], 500_000, 21, 3
+    grid = W.random_grid(np.random.default_rng(77), dim, nb)
+    edges = torch.tensor(grid, dtype=torch.float64, device="cuda")
+    hist = torch.zeros((dim, nb), dtype=torch.float64, device="cuda")
+    res = torch.zeros(4, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        vg.vegas_iterate_noalloc(dim, nb, W.FP64, fid, params, edges.data_ptr(), n, seed, t,
+                                 hist.data_ptr(), res.data_ptr(), stream.cuda_stream)
+    stream.synchronize()
+    r_eager, h_eager = res.cpu().numpy().copy(), hist.cpu().numpy().copy()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        vg.vegas_iterate_noalloc(dim, nb, W.FP64, fid, params, edges.data_ptr(), n, seed, t,
+                                 hist.data_ptr(), res.data_ptr(), stream.cuda_stream)
+    for rep in range(3):
+        res.fill_(-1.0)
+        hist.fill_(-1.0)
+        other = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(res.cpu().numpy(), r_eager), (rep, res.cpu().numpy(), r_eager)
+        assert T.rel_close(hist.cpu().numpy(), h_eager), (rep, T.max_rel(hist.cpu().numpy(), h_eager))
+        assert torch.isfinite(other)
