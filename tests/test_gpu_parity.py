@@ -121,6 +121,32 @@ def test_iterate_shapes_fp64(vg, orc, dim, nb, n):
     assert T.rel_close(hist, h_r), T.max_rel(hist, h_r)
 
 
+@pytest.mark.parametrize("dim,nb,n", SHAPES)
+def test_iterate_shapes_fp32_eval(vg, orc, dim, nb, n):
+    """The same shapes in FP32-eval (binary32 map and integrand, binary64
+    sums) against the binary64 oracle on the same events. Every event falls in
+    the same bin on both sides (the bin index is integer arithmetic on the
+    same random word), so each histogram bin, a sum of non-negative w^2 terms,
+    and I, a mean of non-negative w, carry at most the per-event relative error
+    eps_w of the binary32 weight (twice it for w^2), bounded from the
+    arithmetic by tolerances.fp32_gauss_weight_rtol; sigma gets the
+    cancellation bound of that error. I also lies within 0.1 sigma wherever
+    sigma exceeds the arithmetic's resolution (10 eps_w |I|)."""
+    rng = np.random.default_rng(dim * 1000 + nb)
+    grid = W.random_grid(rng, dim, nb)
+    params = [0.3] + list(rng.uniform(0.3, 0.7, dim))
+    eps_w = T.fp32_gauss_weight_rtol(grid, params)
+    h = _handle(vg, dim, nb, W.F_GAUSS, params, W.FP32_EVAL, grid)
+    I, s = vg.vegas_iterate(h, W.F_GAUSS, n, 123)
+    I_r, s_r, h_r, _ = orc.iterate(grid, W.F_GAUSS, params, n, 123, 0)
+    assert abs(I - I_r) <= eps_w * abs(I_r), (I, I_r, eps_w)
+    if s_r > 10 * eps_w * abs(I_r):
+        assert abs(I - I_r) <= 0.1 * s_r, (I, I_r, s_r)
+    assert T.sigma_close(s, s_r, I_r, n, eps=2 * eps_w), T.sigma_excess(s, s_r, I_r, n, 2 * eps_w)
+    hist = vg.vegas_get_hist(h)
+    assert T.rel_close(hist, h_r, eps=2 * eps_w), (T.max_rel(hist, h_r), 2 * eps_w)
+
+
 @pytest.mark.parametrize("alpha,zeros", [(1.5, 0.0), (1.5, 0.3), (0.0, 0.0), (0.5, 0.1),
                                          (2.0, 0.6)])
 @pytest.mark.parametrize("dim,nb", [(1, 2), (3, 50), (8, 100), (2, 512)])

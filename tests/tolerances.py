@@ -107,6 +107,48 @@ def weights_excess(w, w_ref, kappa=None, eps: float = EPS) -> float:
     return float(np.max(np.abs(w - w_ref) / tol))
 
 
+U32 = 2.0 ** -24  # unit roundoff of binary32
+
+
+def fp32_gauss_weight_rtol(edges, params) -> float:
+    """Relative bound on the FP32-eval Gaussian's per-event weight against the
+    binary64 weight of the same event, over every point of the grid `edges`
+    (params = [a, c_1 .. c_D]). The FP32-eval path forms log2 w = log2 f +
+    log2 J in binary32 and exponentiates it in binary64, so the weight's
+    relative error is ln 2 times the absolute error of that sum:
+    - the binary32 point x_d and centre c_d are each within 3 units of
+      binary32 roundoff u of the exact ones (the bin's lower edge and width
+      rounded, the fraction kept to 23 bits), so |dz_d| <= 6u, z_d = x_d - c_d;
+    - acc = sum z_d^2: |d acc| <= sum 2 |z_d| 6u + (D + 1) u acc;
+    - log2 f = -k acc + c0 (k = log2 e / a^2, c0 = -D log2(a sqrt pi), both
+      rounded): |d log2 f| <= k |d acc| + 2u k acc + 2u |c0| + u |log2 f|;
+    - log2 J = sum over pairs of dimensions of log2((nb Delta_a)(nb Delta_b)):
+      each product within 5u relative (the widths and nb Delta rounded, the
+      product rounded), so its log2 within 5u/ln 2 + 2^-21 (the hardware
+      log2), then D/2 additions each within u |log2 J|.
+    Maxima over the unit cube bound |z_d|, acc and |log2 f|; the grid's
+    narrowest and widest bins bound |log2 J|."""
+    e = np.asarray(edges, dtype=np.float64)
+    D, nb = e.shape[0], e.shape[1] - 1
+    a = float(params[0])
+    c = np.asarray(params[1:1 + D], dtype=np.float64)
+    if c.size < D:
+        c = np.full(D, 0.5)
+    zmax = np.maximum(np.abs(c), np.abs(1.0 - c))
+    acc = float(np.sum(zmax * zmax))
+    k = np.log2(np.e) / (a * a)
+    c0 = abs(D * np.log2(a * np.sqrt(np.pi)))
+    u = U32
+    d_acc = 12.0 * u * float(np.sum(zmax)) + (D + 1) * u * acc
+    log2f = k * acc + c0
+    d_log2f = k * d_acc + 2 * u * k * acc + 2 * u * c0 + u * log2f
+    log2_nbd = np.abs(np.log2(nb * np.diff(e, axis=1)))
+    log2J = float(np.sum(np.max(log2_nbd, axis=1)))
+    pairs = (D + 1) // 2
+    d_log2J = pairs * (5 * u / np.log(2.0) + 2.0 ** -21) + pairs * u * log2J
+    return float(np.log(2.0) * (d_log2f + d_log2J))
+
+
 def event_kappa(orc, edges, fid, params, seed, t, first, count, h: float = 1e-7):
     """kappa(x) = sum_d |x_d d ln f / d x_d| of the oracle's integrand at the
     points of events first .. first+count-1, by central differences of
