@@ -99,3 +99,65 @@ def test_kappa_bound(orc):
     w_alt = np.array([orc.integrand(W.F_LO_TOY, moved[i], params) for i in range(n)]) * jac
     assert T.weights_close(w_alt, w_ref, kap), T.weights_excess(w_alt, w_ref, kap)
     assert kap.max() > 1e3  # points within about 1e-3 of x = 1 occur
+
+
+def _fp32_gauss_weights(orc, grid, params, seed, t, first, count):
+    """The Gaussian's weights by one binary32 evaluation of the steps the
+    bound fp32_gauss_weight_rtol accounts for, written here with numpy: the
+    bin's edge and width rounded to binary32, the point at the centre of its
+    2^-23 cell of the bin by one fused multiply-add, the square sum, log2 f by
+    one fused multiply-add, log2 of pairwise products nb^2 Delta_a Delta_b,
+    their sum, and 2 to that power (a fused multiply-add is the binary64
+    result of exact binary32 operands rounded once to binary32)."""
+    f32 = np.float32
+    e = np.asarray(grid, dtype=np.float64)
+    D, nb = e.shape[0], e.shape[1] - 1
+    x64, k, _ = orc.points(grid, seed, t, first, count)
+    lo = np.take_along_axis(e[:, :-1].T[None, :, :].repeat(count, 0), k[:, None, :], 1)[:, 0, :]
+    delta = np.take_along_axis(np.diff(e, axis=1).T[None, :, :].repeat(count, 0),
+                               k[:, None, :], 1)[:, 0, :]
+    frac = (x64 - lo) / delta
+    cell = np.clip(np.floor(frac * 2.0 ** 23), 0, 2 ** 23 - 1)
+    y = (1.0 + cell * 2.0 ** -23).astype(f32)
+    w32 = delta.astype(f32)
+    e32 = (lo - w32.astype(np.float64) * (1.0 - 2.0 ** -24)).astype(f32)
+    x32 = (y.astype(np.float64) * w32 + e32.astype(np.float64)).astype(f32)
+    a = float(params[0])
+    c32 = np.asarray(params[1:1 + D], dtype=np.float64).astype(f32)
+    acc = np.zeros(count, dtype=f32)
+    for d in range(D):
+        z = (x32[:, d] - c32[d]).astype(f32)
+        acc = (z.astype(np.float64) * z + acc).astype(f32)
+    k32 = f32(np.log2(np.e) / (a * a))
+    c0 = f32(-D * np.log2(a * np.sqrt(np.pi)))
+    log2f = (-np.float64(k32) * acc + np.float64(c0)).astype(f32)
+    l2j = np.zeros(count, dtype=f32)
+    for d in range(0, D, 2):
+        if d + 1 < D:
+            pw = (w32[:, d] * f32(nb * nb)).astype(f32) * w32[:, d + 1]
+        else:
+            pw = (w32[:, d] * f32(nb)).astype(f32)
+        l2j = (l2j + np.log2(pw.astype(np.float64)).astype(f32)).astype(f32)
+    l2 = (l2j + log2f).astype(f32)
+    fl = np.floor(l2)
+    m = np.exp2((l2 - fl).astype(np.float64)).astype(f32)
+    return m.astype(np.float64) * np.exp2(fl.astype(np.float64))
+
+
+def test_fp32_gauss_weight_bound(orc):
+    """A binary32 evaluation of the Gaussian's weights stays within
+    fp32_gauss_weight_rtol of the oracle's binary64 weights at 1, 8 and 32
+    dimensions (random grids, events crossing 2^32), and the bound is not
+    vacuous: the same weights moved by twice it fail."""
+    for dim, nb in ((1, 2), (8, 50), (32, 256)):
+        rng = np.random.default_rng(dim * 1000 + nb)
+        grid = W.random_grid(rng, dim, nb)
+        params = [0.3] + list(rng.uniform(0.3, 0.7, dim))
+        bound = T.fp32_gauss_weight_rtol(grid, params)
+        n, first = 4000, 2**32 - 2000
+        w64 = orc.weights(grid, W.F_GAUSS, params, 9, 1, first, n)
+        w32 = _fp32_gauss_weights(orc, grid, params, 9, 1, first, n)
+        rel = np.abs(w32 / w64 - 1.0)
+        assert rel.max() <= bound, (dim, nb, rel.max(), bound)
+        assert rel.max() > 1e-8  # the evaluation is a binary32 one
+        assert not T.rel_close(w32 * (1.0 + 2.0 * bound), w64, bound)

@@ -125,7 +125,10 @@ def fp32_gauss_weight_rtol(edges, params) -> float:
     - log2 J = sum over pairs of dimensions of log2((nb Delta_a)(nb Delta_b)):
       each product within 5u relative (the widths and nb Delta rounded, the
       product rounded), so its log2 within 5u/ln 2 + 2^-21 (the hardware
-      log2), then D/2 additions each within u |log2 J|.
+      log2), then D/2 additions each within u |log2 J|;
+    - the sum log2 f + log2 J rounded once more (u |log2 f| + u |log2 J|), and
+      2 to the power of its fraction taken by the hardware exp2 (2^-22
+      relative).
     Maxima over the unit cube bound |z_d|, acc and |log2 f|; the grid's
     narrowest and widest bins bound |log2 J|."""
     e = np.asarray(edges, dtype=np.float64)
@@ -141,12 +144,12 @@ def fp32_gauss_weight_rtol(edges, params) -> float:
     u = U32
     d_acc = 12.0 * u * float(np.sum(zmax)) + (D + 1) * u * acc
     log2f = k * acc + c0
-    d_log2f = k * d_acc + 2 * u * k * acc + 2 * u * c0 + u * log2f
+    d_log2f = k * d_acc + 2 * u * k * acc + 2 * u * c0 + 2 * u * log2f
     log2_nbd = np.abs(np.log2(nb * np.diff(e, axis=1)))
     log2J = float(np.sum(np.max(log2_nbd, axis=1)))
     pairs = (D + 1) // 2
-    d_log2J = pairs * (5 * u / np.log(2.0) + 2.0 ** -21) + pairs * u * log2J
-    return float(np.log(2.0) * (d_log2f + d_log2J))
+    d_log2J = pairs * (5 * u / np.log(2.0) + 2.0 ** -21) + (pairs + 1) * u * log2J
+    return float(np.log(2.0) * (d_log2f + d_log2J) + 2.0 ** -22)
 
 
 def event_kappa(orc, edges, fid, params, seed, t, first, count, h: float = 1e-7):
