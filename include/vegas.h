@@ -361,6 +361,14 @@ int vegas_server_wait(vegas_server s, uint64_t ticket, double timeout_s, double 
 /* Per-iteration results of a finished ticket (n_iter entries each). */
 int vegas_server_iterations(vegas_server s, uint64_t ticket, double *I_t, double *sigma_t);
 
+/* Forget a finished ticket: the server frees its record (results, per-
+ * iteration estimates), after which wait and iterations on it return
+ * VEGAS_EINVAL. A server keeps every ticket's record until it is released or
+ * the server is destroyed, so a long-running server releases what it has
+ * read. VEGAS_EBUSY while the ticket has not finished; VEGAS_EINVAL for an
+ * unknown ticket. */
+int vegas_server_release(vegas_server s, uint64_t ticket);
+
 /* Counters: requests completed, events processed, device work items run,
  * peak concurrent integrals. Any pointer may be NULL. */
 int vegas_server_stats(vegas_server s, int64_t *completed, int64_t *events, int64_t *work_items,

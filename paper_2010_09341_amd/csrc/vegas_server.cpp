@@ -722,6 +722,19 @@ int vegas_server_iterations(vegas_server s, uint64_t ticket, double* I_t, double
   return VEGAS_OK;
 }
 
+int vegas_server_release(vegas_server s, uint64_t ticket) {
+  if (!s) return VEGAS_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return VEGAS_EINVAL;
+  // a finished request is referenced by nothing else: collect() removed it
+  // from its slot, its lane and the admission queue, and after a device
+  // error the worker touches no request again
+  if (!it->second->done) return VEGAS_EBUSY;
+  s->reqs.erase(it);
+  return VEGAS_OK;
+}
+
 int vegas_server_stats(vegas_server s, int64_t* completed, int64_t* events, int64_t* work_items,
                        int64_t* peak_active) {
   if (!s) return VEGAS_EINVAL;

@@ -78,6 +78,7 @@ _SIGS = {
     "vegas_server_submit": ([_vp, _vp, _c.POINTER(_u64)]),
     "vegas_server_wait": ([_vp, _u64, _c.c_double, _pd, _pd, _pd, _pd]),
     "vegas_server_iterations": ([_vp, _u64, _pd, _pd]),
+    "vegas_server_release": ([_vp, _u64]),
     "vegas_server_stats": ([_vp, _c.POINTER(_i64), _c.POINTER(_i64), _c.POINTER(_i64),
                             _c.POINTER(_i64)]),
     "vegas_server_destroy": ([_vp]),
@@ -413,6 +414,10 @@ def vegas_server_iterations(s: Server, ticket: int, n_iter: int):
     _check(lib().vegas_server_iterations(s, ticket, _dptr(I_t), _dptr(s_t)),
            "vegas_server_iterations")
     return I_t, s_t
+
+
+def vegas_server_release(s: Server, ticket: int):
+    _check(lib().vegas_server_release(s, ticket), "vegas_server_release")
 
 
 def vegas_server_stats(s: Server):

@@ -121,6 +121,39 @@ def test_admission_by_memory_and_slots(vg):
     vg.vegas_server_destroy(srv)
 
 
+def test_release(vg):
+    """A finished ticket's record is freed by vegas_server_release; reading
+    it afterwards, releasing it twice or an unknown ticket is VEGAS_EINVAL; a
+    ticket still queued (one slot, held by a request of 10 x 5e7 events, a
+    few milliseconds of device work, while the release follows the submission
+    within microseconds) is VEGAS_EBUSY; the other tickets are untouched."""
+    srv = vg.vegas_server_create(1 << 28, 1)
+    long_r = W.Request(0, 0.0, 8, 50, W.F_GAUSS, [0.1], 50_000_000, 10, 1.5, 1, W.FP32_EVAL)
+    short = W.Request(1, 0.0, 3, 20, W.F_GAUSS, [0.2], 10_000, 3, 1.5, 2, W.FP64)
+    tk_long = _submit(vg, srv, long_r)
+    tk_a = _submit(vg, srv, short)
+    tk_b = _submit(vg, srv, short)
+    with pytest.raises(vg.VegasError) as e:
+        vg.vegas_server_release(srv, tk_b)
+    assert e.value.code == vg.VEGAS_EBUSY
+    for tk in (tk_long, tk_a, tk_b):
+        vg.vegas_server_wait(srv, tk, 120.0)
+    I_b, s_b, _, _ = vg.vegas_server_wait(srv, tk_b, 0.0)
+    vg.vegas_server_release(srv, tk_a)
+    for call in (lambda: vg.vegas_server_wait(srv, tk_a, 0.0),
+                 lambda: vg.vegas_server_iterations(srv, tk_a, short.n_iter),
+                 lambda: vg.vegas_server_release(srv, tk_a),
+                 lambda: vg.vegas_server_release(srv, 10**9)):
+        with pytest.raises(vg.VegasError) as e:
+            call()
+        assert e.value.code == vg.VEGAS_EINVAL
+    # the same request in another ticket is unaffected
+    assert vg.vegas_server_wait(srv, tk_b, 0.0)[:2] == (I_b, s_b)
+    vg.vegas_server_release(srv, tk_b)
+    vg.vegas_server_release(srv, tk_long)
+    vg.vegas_server_destroy(srv)
+
+
 def test_served_matches_handle(vg):
     """The serving path and the single-integral path compute the same
     iterations (different launch shapes: agreement to rounding)."""
