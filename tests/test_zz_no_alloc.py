@@ -63,6 +63,13 @@ def test_noalloc_matches_vegas_iterate(vg, orc, prec):
         assert T.sigma_close(r[1], s_h, I_h, n), T.sigma_excess(r[1], s_h, I_h, n)
         assert r[2] == 0.0 and r[3] == t
         assert T.rel_close(hh, hist_h), T.max_rel(hh, hist_h)
+        # without a histogram output (kept in the scratch array): the same
+        # (I, sigma), bit for bit (fixed-order sums)
+        res2 = torch.full((4,), -1.0, dtype=torch.float64, device="cuda")
+        vg.vegas_iterate_noalloc(dim, nb, prec, fid, params, edges.data_ptr(), n, seed, t,
+                                 0, res2.data_ptr(), stream.cuda_stream)
+        stream.synchronize()
+        assert np.array_equal(res2.cpu().numpy(), r), (res2.cpu().numpy(), r)
         if prec == W.FP64:
             I_o, s_o, h_o, bad = orc.iterate(grid, fid, params, n, seed, t)
             assert abs(r[0] - I_o) <= 1e-12 * abs(I_o), (i, r[0], I_o)
