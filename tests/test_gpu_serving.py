@@ -48,6 +48,36 @@ def test_served_fp64_matches_oracle(vg, orc):
     vg.vegas_server_destroy(srv)
 
 
+def test_served_extreme_shapes_fp64(vg, orc):
+    """The serving kernels at the shape limits, FP64 against the oracle: the
+    cell maximum (32 dimensions x 256 bins, the 32-dimension class, one LDS
+    histogram copy) and the minimum (1 dimension, 2 bins, 2 events), served
+    together. At the cell maximum the Gaussian runs one iteration (on the
+    uniform grid: the same events, weights and sums); the refinement at that
+    shape is exercised by three iterations of the sum integrand, whose
+    per-dimension w^2 histograms are smooth. (A 32-dimension Gaussian refined
+    from 2e4 events leaves bins whose compressed weights r_k are tiny; the
+    refined edges then carry the amplified rounding-order difference that the
+    edge bound of the parity tests describes, and its third iteration read
+    2e-12 from the oracle's.)"""
+    srv = vg.vegas_server_create(1 << 28, 8)
+    reqs = [W.Request(0, 0.0, 32, 256, W.F_GAUSS, [0.3], 20_011, 1, 1.5, 5, W.FP64),
+            W.Request(1, 0.0, 32, 256, W.F_SUM, None, 100_003, 3, 1.5, 8, W.FP64),
+            W.Request(2, 0.0, 1, 2, W.F_GAUSS, [0.3], 2, 4, 1.5, 6, W.FP64),
+            W.Request(3, 0.0, 17, 31, W.F_SUM, None, 7_777, 2, 0.5, 7, W.FP64)]
+    tickets = [_submit(vg, srv, r) for r in reqs]
+    for r, tk in zip(reqs, tickets):
+        vg.vegas_server_wait(srv, tk, 120.0)
+        I_t, s_t = vg.vegas_server_iterations(srv, tk, r.n_iter)
+        I_r, s_r, _, _ = orc.run(r.dim, r.nb, r.fid, r.params, r.n_events, r.seed, r.n_iter,
+                                 r.alpha)
+        assert np.all(np.abs(I_t - I_r) <= 1e-12 * np.abs(I_r)), (r.index, I_t, I_r)
+        assert T.sigma_close(s_t, s_r, I_r, r.n_events), (r.index,
+                                                           T.sigma_excess(s_t, s_r, I_r, r.n_events))
+        vg.vegas_server_release(srv, tk)
+    vg.vegas_server_destroy(srv)
+
+
 def test_alone_equals_in_the_mix(vg):
     """20 requests from the serving trace, each run alone on its own server,
     then all 200 trace requests together: the 20 agree within 1e-12."""
