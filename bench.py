@@ -145,6 +145,16 @@ def traffic_from_profile():
     return float(m_b.group(1))
 
 
+def optional(name, fn, *args):
+    """A section of the report beside the headline: an exception in it is
+    recorded in the report (and logged) instead of ending the run."""
+    try:
+        return fn(*args)
+    except Exception as e:  # noqa: BLE001 - recorded, not swallowed
+        log(f"{name} failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
@@ -267,7 +277,8 @@ def main():
     # fork-safe).
     cpu_all = None
     if not args.no_cpu:
-        cpu_all = {name: cpu_baseline_all_cores(W.WORKLOADS[name])
+        cpu_all = {name: optional(f"{name} oracle on all cores", cpu_baseline_all_cores,
+                                  W.WORKLOADS[name])
                    for name in [wl.name] + others}
 
     from paper_2010_09341_amd import vegas as vg
@@ -296,11 +307,14 @@ def main():
     # 20 take 0.58 ms).
     per_other = {}
     t_gpu0 = time.perf_counter()
-    for name in others:
-        o = W.WORKLOADS[name]
+    def other_workload(o):
         res_o = measure(vg, W, o, args.steps, min(args.warmup, 5), min(args.latency_reps, 100))
-        per_other[name] = workload_summary(W, o, res_o, args.steps)
-        per_other[name]["fp64_I_t"] = [float(v) for v in res_o[W.FP64]["I_t"]]
+        summary = workload_summary(W, o, res_o, args.steps)
+        summary["fp64_I_t"] = [float(v) for v in res_o[W.FP64]["I_t"]]
+        return summary
+
+    for name in others:
+        per_other[name] = optional(name, other_workload, W.WORKLOADS[name])
     gpu_busy_before_s = time.perf_counter() - t_gpu0
 
     results = measure(vg, W, wl, args.steps, args.warmup, args.latency_reps)
@@ -382,13 +396,16 @@ def main():
         },
     }
     if not args.no_extras:
-        out["latency_ms"]["gauss4d_fp64"] = small_latency(vg, W, args.latency_reps)
+        out["latency_ms"]["gauss4d_fp64"] = optional("gauss4d latency", small_latency, vg, W,
+                                                     args.latency_reps)
         if wl.name == "gauss8d":
-            out["one_gpu_share_of_8"] = gpu_share(vg, W, wl, max(20, args.steps // 4))
-        out["events_limit_sweep"] = events_limit_sweep(vg, W, wl, max(3, args.steps // 4))
+            out["one_gpu_share_of_8"] = optional("one GPU share", gpu_share, vg, W, wl,
+                                                 max(20, args.steps // 4))
+        out["events_limit_sweep"] = optional("events_limit sweep", events_limit_sweep, vg, W, wl,
+                                             max(3, args.steps // 4))
     if wl.fid == W.F_GAUSS and not args.no_extras:
-        out["user_integrand"] = user_integrand_section(
-            vg, W, wl, max(3, args.steps // 4),
+        out["user_integrand"] = optional(
+            "run-time integrand", user_integrand_section, vg, W, wl, max(3, args.steps // 4),
             {W.FP32_EVAL: value, W.FP64: value64})
     closed = W.gauss_closed_form(wl.dim, wl.params[0]) if wl.fid == W.F_GAUSS else None
     if closed is not None:
@@ -397,22 +414,29 @@ def main():
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(wl, r64["I_t"], r64["s_t"])
-        out["cpu_baseline"]["all_cores"] = cpu_all[wl.name]
-        # bounded one-core samples and all-core rates of the other workloads
-        out["cpu_baseline"]["workloads"] = {
-            name: {"one_core": cpu_sample(W.WORKLOADS[name]), "all_cores": cpu_all[name]}
-            for name in others}
-        # the GPU's FP64 iterations of the other workloads against the oracle's
-        # whole run of the same workload (stored by tests/golden/make_golden.py)
-        for name in others:
-            ref = golden_I_t(name)
-            if ref is not None:
-                got = np.asarray(per_workload[name]["fp64_I_t"])
-                out["cpu_baseline"]["workloads"][name]["fp64_gpu_vs_oracle_max_rel_err_I_t"] = \
-                    float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+        def cpu_section():
+            cb = cpu_baseline(wl, r64["I_t"], r64["s_t"])
+            cb["all_cores"] = cpu_all[wl.name]
+            # bounded one-core samples and all-core rates of the other workloads
+            cb["workloads"] = {
+                name: {"one_core": optional(f"{name} cpu sample", cpu_sample, W.WORKLOADS[name]),
+                       "all_cores": cpu_all[name]}
+                for name in others}
+            # the GPU's FP64 iterations of the other workloads against the
+            # oracle's whole run of the same workload (stored by
+            # tests/golden/make_golden.py)
+            for name in others:
+                ref = golden_I_t(name)
+                got = per_workload[name].get("fp64_I_t")
+                if ref is not None and got is not None:
+                    cb["workloads"][name]["fp64_gpu_vs_oracle_max_rel_err_I_t"] = \
+                        float(np.max(np.abs(np.asarray(got) - ref) / np.abs(ref)))
+            return cb
+
+        out["cpu_baseline"] = optional("cpu baseline", cpu_section)
     if not args.no_serving:
-        out["serving"] = serving_section(vg, W, args.serving_requests)
+        out["serving"] = optional("serving", serving_section, vg, W, args.serving_requests)
     # the paper's own timings (Table 1), context only: another machine, an
     # integral and event count it does not state
     out["paper_context"] = {
