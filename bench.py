@@ -405,6 +405,13 @@ def main():
         if wl.name == "gauss8d":
             out["one_gpu_share_of_8"] = optional("one GPU share", gpu_share, vg, W, wl,
                                                  max(20, args.steps // 4))
+            # the same share of the other configured workloads (N/8 events
+            # per iteration each)
+            if isinstance(out["one_gpu_share_of_8"], dict) and others:
+                out["one_gpu_share_of_8"]["workloads"] = {
+                    name: optional(f"{name} one GPU share", gpu_share, vg, W, W.WORKLOADS[name],
+                                   max(5, args.steps // 4))
+                    for name in others}
         out["events_limit_sweep"] = optional("events_limit sweep", events_limit_sweep, vg, W, wl,
                                              max(3, args.steps // 4))
     if wl.fid == W.F_GAUSS and not args.no_extras:
