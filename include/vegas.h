@@ -264,9 +264,9 @@ int vegas_dump_weights(vegas_h h, int integrand_id, uint64_t seed, uint64_t firs
  * held until the process ends; each call clears what must start at zero.
  * Calls that overlap on one GPU (other streams, other threads) race on that
  * array and must be serialised by the caller. VEGAS_EINVAL for a shape
- * beyond VEGAS_MAX_CELLS (the array's limit), a run-time integrand id,
- * n_events < 2 or a NULL edges_dev/result_dev; VEGAS_EDEVICE on a HIP
- * error. */
+ * beyond VEGAS_MAX_CELLS (the array's limit), an unknown precision, a
+ * run-time integrand id, parameters the integrand does not take, n_events
+ * < 2 or a NULL edges_dev/result_dev; VEGAS_EDEVICE on a HIP error. */
 #define VEGAS_NOALLOC_SCRATCH_BYTES (1 << 20)
 int vegas_iterate_noalloc(int dim, int n_bins, int prec, int integrand_id, const double *params,
                           int n_params, const double *edges_dev, int64_t n_events, uint64_t seed,
