@@ -95,7 +95,8 @@ def test_noalloc_rejections(vg):
         assert e.value.code == vg.VEGAS_EINVAL, (dim, nb, prec, fid, n)
 
 
-def test_noalloc_under_graph_capture(vg):
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32_EVAL], ids=["fp64", "fp32_eval"])
+def test_noalloc_under_graph_capture(vg, prec):
     """The callers it is for: one iteration captured into a hipGraph by torch
     (global capture mode, in which an allocation anywhere in the process makes
     the capture fail), replayed three times with eager work and
@@ -110,13 +111,13 @@ def test_noalloc_under_graph_capture(vg):
     res = torch.zeros(4, dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        vg.vegas_iterate_noalloc(dim, nb, W.FP64, fid, params, edges.data_ptr(), n, seed, t,
+        vg.vegas_iterate_noalloc(dim, nb, prec, fid, params, edges.data_ptr(), n, seed, t,
                                  hist.data_ptr(), res.data_ptr(), stream.cuda_stream)
     stream.synchronize()
     r_eager, h_eager = res.cpu().numpy().copy(), hist.cpu().numpy().copy()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
-        vg.vegas_iterate_noalloc(dim, nb, W.FP64, fid, params, edges.data_ptr(), n, seed, t,
+        vg.vegas_iterate_noalloc(dim, nb, prec, fid, params, edges.data_ptr(), n, seed, t,
                                  hist.data_ptr(), res.data_ptr(), stream.cuda_stream)
     for rep in range(3):
         res.fill_(-1.0)
