@@ -42,8 +42,14 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
     sequence of the method, counted operation by operation, one issue slot
     per instruction (issued instructions are measured separately with
     SQ_INSTS_VALU; the difference is loop and compiler overhead). Counted
-    for the Gaussian in both precisions and for the LO toy and RAMBO 2->4 in
-    FP32-eval (their configured precision); None otherwise.
+    for the Gaussian and the LO toy in both precisions and for RAMBO 2->4 in
+    FP32-eval (its configured precision); None otherwise. Binary64 square
+    roots and divisions count as the compiler's correctly rounded sequences
+    for gfx950: square root 18 (reciprocal square root 1; the scaling of
+    small arguments: compare, two selects, two ldexp = 5; Newton steps: 7
+    fmas and 2 products = 9; the special-case class test and two selects =
+    3), division 11 (two scale steps, reciprocal, 5 fmas, a product, the
+    fused correction and the fix-up).
 
     Common to every integrand:
       Philox4x32-10 per 4 dimensions: 10 rounds x (2 v_mad_u64_u32 + 2
@@ -78,6 +84,14 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
       product and its cube (3); rsqrt of x1 x2 and its product (2);
       s^ - m^2 (1); (dm^2 + (m G)^2) s^ (2); 1 + c^2 (1), reciprocal (1) and
       three products (3); cut compare and select (2) = 20
+    LO toy (FP64): phi is unused, so its point is never formed (the map's
+      conversion and fma of that dimension, -2); c = fma (1); x1 x2 and s^
+      (2); the cut sqrt(s^) > 20: square root (18), compare (1) and the
+      final two-word select (2); (1 - x1)(1 - x2) (3); s^ - m^2 (1); the
+      numerator y^3 (1 + c^2) norm: square, cube, fma, two products (5); the
+      denominator sqrt(x1 x2) (dm^2 + (m G)^2) s^: square root (18), fma and
+      two products (3); the division (11); the product by J (1)
+      = 19 + 2 x 18 + 11 = 66
     RAMBO 2->4 (FP32), per particle: cos theta = min(fma, 1) (2); sin theta
       = sqrt(max(fma, 0)) (3); sin, cos (2); energy -ln(u u') = max(-log2 x
       ln 2, 0) with the product (4); three momentum components (3); then
@@ -97,8 +111,10 @@ def alg_valu_per_event(dim: int, prec: int, fid: int = 2):
         common += 4 * dim - 1
     if fid == 2:
         return common + 2 * dim + (2 + 6 if prec == 1 else 21)
-    if prec != 1:
+    if prec != 1 and not (fid == 3 and dim == 4):
         return None
+    if fid == 3 and dim == 4 and prec != 1:
+        return common - 2 + 19 + 2 * 18 + 11
     if fid == 3 and dim == 4:
         return common + 20 + 6 + 2
     if fid == 4 and dim == 16:
@@ -240,9 +256,11 @@ def workload_summary(W, wl, res, steps):
                     "latency_ms_p50_p99": [pct(r["lat"], 50) * 1e3, pct(r["lat"], 99) * 1e3],
                     "I": r["comb"][0], "sigma": r["comb"][1]}
         if not slots:
-            out[key]["frac_note"] = ("no algorithmic count: the workload's configured precision is "
-                                     "FP32-eval; this binary64 run is its matched-sigma comparison "
-                                     "and oracle-parity path, reported by time")
+            out[key]["frac_note"] = ("no algorithmic count for this binary64 loop (the workload's "
+                                     "configured precision is FP32-eval; its compiled loop carries "
+                                     "register-pressure overhead, SGPR spills restored with "
+                                     "v_readlane and 64-bit moves, that an operation count would "
+                                     "not hold); reported by time")
     out["sigma_ratio"] = s32 / s64
     out["matched"] = abs(s32 / s64 - 1.0) < 1e-2
     out["fp32_minus_fp64_over_sigma"] = (I32 - I64) / s64
