@@ -184,6 +184,51 @@ def test_release(vg):
     vg.vegas_server_destroy(srv)
 
 
+def test_concurrent_clients(vg):
+    """Server calls from several threads at once (the library's calls
+    release the interpreter lock): four threads each submit, wait for and
+    release 12 trace requests, interleaved with each other and with a
+    statistics reader; every result agrees with the same request served alone
+    as in the mix test (same chunks and partial slots; the refined grids
+    agree to rounding, the histogram being summed with atomics)."""
+    import threading
+    trace = W.serving_trace(48, rate_per_s=1e9, seed=11, max_events=200_000)
+    alone = {}
+    for r in trace[::6]:
+        srv = vg.vegas_server_create(1 << 28, 4)
+        tk = _submit(vg, srv, r)
+        alone[r.index] = vg.vegas_server_wait(srv, tk, 120.0)[:2]
+        vg.vegas_server_destroy(srv)
+    srv = vg.vegas_server_create(1 << 28, 16)
+    got, errors = {}, []
+
+    def client(part):
+        try:
+            mine = [(r, _submit(vg, srv, r)) for r in part]
+            for r, tk in mine:
+                got[r.index] = vg.vegas_server_wait(srv, tk, 120.0)[:2]
+                vg.vegas_server_release(srv, tk)
+                vg.vegas_server_stats(srv)
+        except Exception as e:  # noqa: BLE001 - reported by the assertion below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=client, args=(trace[i::4],)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=180.0)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
+    assert sorted(got) == [r.index for r in trace]
+    by_index = {r.index: r for r in trace}
+    for i, (I_a, s_a) in alone.items():
+        I_g, s_g = got[i]
+        assert abs(I_g - I_a) <= 1e-12 * abs(I_a), (i, I_g, I_a)
+        assert T.sigma_close(s_g, s_a, I_a, by_index[i].n_events), (i, s_g, s_a)
+    assert vg.vegas_server_stats(srv)[0] == len(trace)
+    vg.vegas_server_destroy(srv)
+
+
 def test_served_matches_handle(vg):
     """The serving path and the single-integral path compute the same
     iterations (different launch shapes: agreement to rounding)."""
