@@ -116,3 +116,31 @@ def test_integrand_compile_without_gpu():
     assert L.vegas_integrand_compile(src.encode(), -1, ctypes.byref(fid), None, 0) == -1
     assert L.vegas_integrand_compile(src.encode(), 0, None, None, 0) == -1
     assert fid.value == -1
+
+
+def test_integrand_compile_from_threads():
+    """vegas_integrand_compile from four threads at once (the library call
+    releases the interpreter lock): four distinct ids, each within the
+    run-time range."""
+    import threading
+    from paper_2010_09341_amd import vegas as vg
+    ids, errors = [], []
+
+    def compile_one(k):
+        src = (f"__device__ double vegas_user_f64(const double* x, int dim, const double* p)"
+               f" {{ return x[0] + {k}.0; }}\n"
+               f"__device__ float vegas_user_f32(const float* x, int dim, const float* p)"
+               f" {{ return x[0] + {k}.0f; }}\n")
+        try:
+            ids.append(vg.vegas_integrand_compile(src, 2))
+        except Exception as e:  # noqa: BLE001 - reported by the assertion below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=compile_one, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=300.0)
+    assert not errors, errors
+    assert len(set(ids)) == 4
+    assert all(vg.VEGAS_F_USER <= i < vg.VEGAS_F_USER + vg.VEGAS_MAX_USER for i in ids)

@@ -563,3 +563,37 @@ def test_rebind_workspace_after_captured_run(vg, orc):
     got = vg.vegas_get_grid(h)
     assert T.edges_close(got, e_r, e_prev, h_last, wl.alpha), \
         T.edges_excess(got, e_r, e_prev, h_last, wl.alpha)
+
+
+def test_handles_in_threads(vg, orc):
+    """Distinct handles are independent: four threads each run a whole FP64
+    run (captured graph, own stream) on their own handle at the same time;
+    every run matches the oracle's at the bounds the single-threaded run
+    tests use."""
+    import threading
+    runs = [(3, 20, W.F_GAUSS, [0.2], 40_000, 1, 4), (5, 32, W.F_BW_FLAT, [0.4, 0.02], 30_011, 2, 3),
+            (8, 50, W.F_GAUSS, [0.1], 100_000, 3, 3), (2, 64, W.F_SUM, None, 20_000, 4, 5)]
+    got, errors = {}, []
+
+    def worker(i, dim, nb, fid, params, n, seed, n_iter):
+        try:
+            h = _handle(vg, dim, nb, fid, params, W.FP64)
+            for _ in range(3):  # the later runs replay the captured graph
+                vg.vegas_reset(h)
+                got[i] = vg.vegas_run(h, fid, n, seed, n_iter, 1.5)
+            vg.vegas_destroy(h)
+        except Exception as e:  # noqa: BLE001 - reported by the assertion below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(i,) + r) for i, r in enumerate(runs)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=180.0)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
+    for i, (dim, nb, fid, params, n, seed, n_iter) in enumerate(runs):
+        I_r, s_r, _, _ = orc.run(dim, nb, fid, params, n, seed, n_iter, 1.5)
+        I_t, s_t = got[i]
+        assert _close(I_t, I_r), (i, I_t, I_r)
+        assert T.sigma_close(s_t, s_r, I_r, n), (i, T.sigma_excess(s_t, s_r, I_r, n))
