@@ -363,7 +363,8 @@ int vegas_server_iterations(vegas_server s, uint64_t ticket, double *I_t, double
 
 /* Forget a finished ticket: the server frees its record (results, per-
  * iteration estimates), after which wait and iterations on it return
- * VEGAS_EINVAL. A server keeps every ticket's record until it is released or
+ * VEGAS_EINVAL (a wait on it in another thread returns VEGAS_EINVAL too, if
+ * the release comes first). A server keeps every ticket's record until it is released or
  * the server is destroyed, so a long-running server releases what it has
  * read. VEGAS_EBUSY while the ticket has not finished; VEGAS_EINVAL for an
  * unknown ticket. */

@@ -690,15 +690,22 @@ int vegas_server_wait(vegas_server s, uint64_t ticket, double timeout_s, double*
                       double* chi2_dof, double* latency_s) {
   if (!s) return VEGAS_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return VEGAS_EINVAL;
-  Req* q = it->second.get();
+  if (s->reqs.find(ticket) == s->reqs.end()) return VEGAS_EINVAL;
+  // The ticket is looked up again at every wake-up: another thread may have
+  // released it (and freed its record) once it finished, before this one
+  // reacquired the lock.
+  Req* q = nullptr;
+  auto ready = [&] {
+    const auto it = s->reqs.find(ticket);
+    q = it == s->reqs.end() ? nullptr : it->second.get();
+    return !q || q->done;
+  };
   if (timeout_s < 0) {
-    s->cv_done.wait(lk, [&] { return q->done; });
-  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
-                                  [&] { return q->done; })) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
     return VEGAS_EBUSY;
   }
+  if (!q) return VEGAS_EINVAL;  // released by another thread meanwhile
   if (q->status == VEGAS_EDEVICE) return VEGAS_EDEVICE;
   if (I) *I = q->I;
   if (sigma) *sigma = q->sigma;

@@ -184,6 +184,38 @@ def test_release(vg):
     vg.vegas_server_destroy(srv)
 
 
+def test_release_while_another_thread_waits(vg):
+    """A ticket released by one thread while another thread waits on it: the
+    waiter returns the result (it read it first) or VEGAS_EINVAL (the release
+    came first), never a freed record; 24 rounds at different timings."""
+    import threading
+    srv = vg.vegas_server_create(1 << 28, 4)
+    outcomes = []
+    for i in range(24):
+        r = W.Request(i, 0.0, 4, 30, W.F_GAUSS, [0.2], 20_000 + 5_000 * (i % 6), 3, 1.5, i,
+                      W.FP32_EVAL)
+        tk = _submit(vg, srv, r)
+        got = []
+
+        def waiter(tk=tk, got=got):
+            try:
+                got.append(("ok", vg.vegas_server_wait(srv, tk, 60.0)[:2]))
+            except vg.VegasError as e:
+                got.append(("err", e.code))
+
+        t = threading.Thread(target=waiter)
+        t.start()
+        ref = vg.vegas_server_wait(srv, tk, 60.0)[:2]
+        vg.vegas_server_release(srv, tk)
+        t.join(timeout=60.0)
+        assert not t.is_alive() and len(got) == 1
+        kind, val = got[0]
+        assert (kind == "ok" and val == ref) or (kind == "err" and val == vg.VEGAS_EINVAL), got
+        outcomes.append(kind)
+    vg.vegas_server_destroy(srv)
+    assert len(outcomes) == 24
+
+
 def test_concurrent_clients(vg):
     """Server calls from several threads at once (the library's calls
     release the interpreter lock): four threads each submit, wait for and
