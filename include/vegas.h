@@ -411,7 +411,8 @@ int vegas_server_chains(vegas_server s, int64_t *chains);
  * on it (an integral's estimate is the same in any lane and any mix). */
 int vegas_server_set_lanes(vegas_server s, int lanes);
 
-/* Drain all queued work, then release the server. */
+/* Drain all queued work, then release the server. No other call on the
+ * server may be in progress (a wait in another thread included) or follow. */
 int vegas_server_destroy(vegas_server s);
 
 #ifdef __cplusplus
